@@ -1,0 +1,415 @@
+/*
+ * oracle.c -- plain, slow, obviously-correct FP64 CPU reference for SP2
+ * density-matrix purification.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; it shares no code, header, table or constant with the
+ * GPU path.  Only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it.
+ *
+ * What it computes (paper: Fattebert et al., "Hybrid programming-model
+ * strategies for GPU offloading of electronic structure calculation kernels",
+ * arXiv 2401.13772):
+ *
+ *   oracle_jacobi_dm     the definition of the zero-temperature density
+ *                        matrix: eigen-decompose the symmetric H, then
+ *                        D = sum over the n_occ lowest eigenpairs of v v^T
+ *                        (Section "Single-particle density matrix ...",
+ *                        Fermi-Dirac equation with beta -> infinity and mu in
+ *                        the gap).  The eigen-decomposition is the textbook
+ *                        cyclic-by-row Jacobi method.
+ *   oracle_gershgorin    spectral bounds by Gershgorin circles (Section
+ *                        "Distributed matrices"; used as emin/emax in the SP2
+ *                        listing of Section "SP2 solver").
+ *   oracle_sp2           the SP2 recursion of Section "SP2 solver" (the
+ *                        equations for D_0 and D_{m+1}, and the listing's
+ *                        branch rule), with plain triple-loop products.
+ *   oracle_sp2_spectral  the same recursion applied to the eigenvalues of H
+ *                        (a polynomial of H acts on each eigenvalue alone).
+ *   oracle_sp2_step_entries  single entries of one SP2 step, for sampled
+ *                        checks at sizes where the full loop is too slow.
+ *
+ * Readings where the paper is silent (also listed in the design notes):
+ *   - H is used through its symmetric part Hs = (H + H^T)/2.
+ *   - D_0 uses Gershgorin bounds (emin, emax) of Hs, computed in FP64.
+ *   - The branch uses tr(X_m) taken before the squaring; the tie
+ *     tr - n_occ == 0 takes X <- 2X - X^2 (the listing's "<=").
+ *   - n_occ plays the role of the listing's number of electrons.
+ *   - The convergence check elided in the listing is: e_m = ||X_m^2 - X_m||_F;
+ *     stop after the update when e_m <= tol; stop as "stagnated" when
+ *     m >= 2, e_m >= e_{m-2} and e_m < 0.1; otherwise stop at max_iter.
+ *   - n_occ == 0 gives D = 0 and n_occ == n gives D = I with no iteration.
+ *   - emax == emin with 0 < n_occ < n is degenerate (no unique D).
+ *
+ * Precision: IEEE double throughout.  Build with -ffp-contract=off so every
+ * operation is rounded as written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum {
+    ORACLE_OK = 0,
+    ORACLE_NOT_CONVERGED = 1,
+    ORACLE_STAGNATED = 2,
+    ORACLE_INVALID = -1,
+    ORACLE_DEGENERATE = -2,
+    ORACLE_NOMEM = -5
+};
+
+typedef struct {
+    int32_t status;
+    int32_t iterations;
+    double emin, emax;
+    double trace;          /* trace of the returned D */
+    double idempotency;    /* e of the last step taken: ||X_m^2 - X_m||_F */
+    uint64_t branch_mask[2]; /* bit m set when step m used 2X - X^2 */
+} oracle_sp2_result;
+
+int oracle_version(void) { return 1; }
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static int all_finite(const double* A, long count)
+{
+    for (long i = 0; i < count; ++i)
+        if (!isfinite(A[i])) return 0;
+    return 1;
+}
+
+/* Hs[i][j] = (H[i][j] + H[j][i]) / 2 */
+static void symmetric_part(const double* H, int n, double* Hs)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            Hs[(long)i * n + j] = (H[(long)i * n + j] + H[(long)j * n + i]) / 2.0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Gershgorin circles: every eigenvalue of Hs lies in some disc centred at  */
+/* Hs_ii with radius R_i = sum_{j != i} |Hs_ij|.                            */
+/* ---------------------------------------------------------------------- */
+int oracle_gershgorin(const double* H, int n, double* emin, double* emax)
+{
+    if (n <= 0 || !H || !emin || !emax) return ORACLE_INVALID;
+    if (!all_finite(H, (long)n * n)) return ORACLE_INVALID;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        double radius = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            radius += fabs((H[(long)i * n + j] + H[(long)j * n + i]) / 2.0);
+        }
+        double centre = H[(long)i * n + i];   /* (h + h)/2 == h exactly */
+        if (centre - radius < lo) lo = centre - radius;
+        if (centre + radius > hi) hi = centre + radius;
+    }
+    *emin = lo;
+    *emax = hi;
+    return ORACLE_OK;
+}
+
+/* D_0 = (emax I - Hs) / (emax - emin), one division per entry. */
+void oracle_sp2_init(const double* H, int n, double emin, double emax, double* X0)
+{
+    double width = emax - emin;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double hs = (H[(long)i * n + j] + H[(long)j * n + i]) / 2.0;
+            double a = (i == j) ? (emax - hs) : (0.0 - hs);
+            X0[(long)i * n + j] = a / width;
+        }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Cyclic-by-row Jacobi eigenvalue method for a symmetric matrix.           */
+/* Each rotation J(p,q,theta) zeroes a_pq in J^T A J (the classical 2x2     */
+/* symmetric Schur decomposition); sweeps repeat until the off-diagonal      */
+/* mass is negligible.  On return w is ascending and column i of V (row-     */
+/* major n x n) is the eigenvector of w[i].                                  */
+/* ---------------------------------------------------------------------- */
+int oracle_jacobi_eigh(const double* A_in, int n, double* w, double* V, int max_sweeps,
+                       int* sweeps_out)
+{
+    if (n <= 0 || !A_in || !w || !V) return ORACLE_INVALID;
+    if (!all_finite(A_in, (long)n * n)) return ORACLE_INVALID;
+    double* a = (double*)malloc(sizeof(double) * (size_t)n * n);
+    if (!a) return ORACLE_NOMEM;
+    symmetric_part(A_in, n, a);
+    for (long i = 0; i < (long)n * n; ++i) V[i] = 0.0;
+    for (int i = 0; i < n; ++i) V[(long)i * n + i] = 1.0;
+
+    double fro2 = 0.0;
+    for (long i = 0; i < (long)n * n; ++i) fro2 += a[i] * a[i];
+    double thresh = 1e-15 * 1e-15 * fro2;
+
+    int sweep = 0;
+    for (sweep = 0; sweep < max_sweeps; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += 2.0 * a[(long)p * n + q] * a[(long)p * n + q];
+        if (off <= thresh) break;
+        int rotations = 0;
+        for (int p = 0; p < n - 1; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                double apq = a[(long)p * n + q];
+                if (apq == 0.0) continue;
+                double app = a[(long)p * n + p], aqq = a[(long)q * n + q];
+                double tau = (aqq - app) / (2.0 * apq);
+                double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                double c = 1.0 / sqrt(1.0 + t * t);
+                double s = t * c;
+                /* columns: A <- A J */
+                for (int k = 0; k < n; ++k) {
+                    double akp = a[(long)k * n + p], akq = a[(long)k * n + q];
+                    a[(long)k * n + p] = c * akp - s * akq;
+                    a[(long)k * n + q] = s * akp + c * akq;
+                }
+                /* rows: A <- J^T A */
+                for (int k = 0; k < n; ++k) {
+                    double apk = a[(long)p * n + k], aqk = a[(long)q * n + k];
+                    a[(long)p * n + k] = c * apk - s * aqk;
+                    a[(long)q * n + k] = s * apk + c * aqk;
+                }
+                a[(long)p * n + q] = 0.0;
+                a[(long)q * n + p] = 0.0;
+                /* eigenvectors: V <- V J */
+                for (int k = 0; k < n; ++k) {
+                    double vkp = V[(long)k * n + p], vkq = V[(long)k * n + q];
+                    V[(long)k * n + p] = c * vkp - s * vkq;
+                    V[(long)k * n + q] = s * vkp + c * vkq;
+                }
+                ++rotations;
+            }
+        }
+        if (rotations == 0) break;
+    }
+    if (sweeps_out) *sweeps_out = sweep;
+
+    /* sort ascending (selection sort on the diagonal, permuting V's columns) */
+    for (int i = 0; i < n; ++i) w[i] = a[(long)i * n + i];
+    for (int i = 0; i < n - 1; ++i) {
+        int best = i;
+        for (int j = i + 1; j < n; ++j)
+            if (w[j] < w[best]) best = j;
+        if (best != i) {
+            double tw = w[i]; w[i] = w[best]; w[best] = tw;
+            for (int k = 0; k < n; ++k) {
+                double tv = V[(long)k * n + i];
+                V[(long)k * n + i] = V[(long)k * n + best];
+                V[(long)k * n + best] = tv;
+            }
+        }
+    }
+    free(a);
+    return ORACLE_OK;
+}
+
+/* D = sum_{i < n_occ} v_i v_i^T from the ascending eigenpairs of H.
+ * w (length n) receives the eigenvalues; gap receives w[n_occ] - w[n_occ-1]
+ * (0 when n_occ is 0 or n). */
+int oracle_jacobi_dm(const double* H, int n, int n_occ, double* D, double* w, double* gap,
+                     int* sweeps)
+{
+    if (n <= 0 || n_occ < 0 || n_occ > n || !H || !D || !w) return ORACLE_INVALID;
+    double* V = (double*)malloc(sizeof(double) * (size_t)n * n);
+    if (!V) return ORACLE_NOMEM;
+    int st = oracle_jacobi_eigh(H, n, w, V, 100, sweeps);
+    if (st != ORACLE_OK) { free(V); return st; }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < n_occ; ++k) acc += V[(long)i * n + k] * V[(long)j * n + k];
+            D[(long)i * n + j] = acc;
+        }
+    if (gap) *gap = (n_occ > 0 && n_occ < n) ? w[n_occ] - w[n_occ - 1] : 0.0;
+    free(V);
+    return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* SP2 on the matrix                                                        */
+/* ---------------------------------------------------------------------- */
+
+/* S = X X (n x n, row-major), summing over k in increasing order. */
+static void square(const double* X, double* S, int n, int nthreads)
+{
+    (void)nthreads;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+    for (int i = 0; i < n; ++i) {
+        double* Si = S + (long)i * n;
+        for (int j = 0; j < n; ++j) Si[j] = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double xik = X[(long)i * n + k];
+            const double* Xk = X + (long)k * n;
+            for (int j = 0; j < n; ++j) Si[j] += xik * Xk[j];
+        }
+    }
+}
+
+static double trace_of(const double* X, int n)
+{
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += X[(long)i * n + i];
+    return t;
+}
+
+/*
+ * Run SP2 on H.  D (n x n) receives the last iterate.  tr_hist / e_hist (may be
+ * NULL, length >= max_iter) receive tr(X_m) and e_m per step.  nthreads sets the
+ * OpenMP threads of the products (1 = serial).
+ */
+int oracle_sp2(const double* H, int n, int n_occ, double tol, int max_iter, int nthreads,
+               double* D, oracle_sp2_result* res, double* tr_hist, double* e_hist)
+{
+    if (!res) return ORACLE_INVALID;
+    memset(res, 0, sizeof(*res));
+    if (n <= 0 || !H || !D || n_occ < 0 || n_occ > n || !(tol > 0.0) || max_iter < 0) {
+        res->status = ORACLE_INVALID;
+        return ORACLE_INVALID;
+    }
+    double emin, emax;
+    int st = oracle_gershgorin(H, n, &emin, &emax);
+    if (st != ORACLE_OK) { res->status = st; return st; }
+    res->emin = emin;
+    res->emax = emax;
+
+    long nn = (long)n * n;
+    if (n_occ == 0 || n_occ == n) {
+        for (long i = 0; i < nn; ++i) D[i] = 0.0;
+        if (n_occ == n)
+            for (int i = 0; i < n; ++i) D[(long)i * n + i] = 1.0;
+        res->trace = (double)n_occ;
+        res->status = ORACLE_OK;
+        return ORACLE_OK;
+    }
+    if (!(emax > emin)) { res->status = ORACLE_DEGENERATE; return ORACLE_DEGENERATE; }
+
+    double* X = (double*)malloc(sizeof(double) * (size_t)nn);
+    double* S = (double*)malloc(sizeof(double) * (size_t)nn);
+    double* e = (double*)malloc(sizeof(double) * (size_t)(max_iter > 0 ? max_iter : 1));
+    if (!X || !S || !e) { free(X); free(S); free(e); res->status = ORACLE_NOMEM; return ORACLE_NOMEM; }
+
+    oracle_sp2_init(H, n, emin, emax, X);
+    int status = ORACLE_NOT_CONVERGED;
+    int m;
+    for (m = 0; m < max_iter; ++m) {
+        double tr = trace_of(X, n);
+        square(X, S, n, nthreads);
+        double e2 = 0.0;
+        for (long i = 0; i < nn; ++i) {
+            double d = S[i] - X[i];
+            e2 += d * d;
+        }
+        e[m] = sqrt(e2);
+        int grow = (tr - (double)n_occ <= 0.0);   /* tie goes to 2X - X^2 */
+        if (grow) {
+            for (long i = 0; i < nn; ++i) X[i] = 2.0 * X[i] - S[i];
+            if (m < 128) res->branch_mask[m / 64] |= (uint64_t)1 << (m % 64);
+        } else {
+            for (long i = 0; i < nn; ++i) X[i] = S[i];
+        }
+        if (tr_hist) tr_hist[m] = tr;
+        if (e_hist) e_hist[m] = e[m];
+        res->idempotency = e[m];
+        if (e[m] <= tol) { status = ORACLE_OK; ++m; break; }
+        if (m >= 2 && e[m] >= e[m - 2] && e[m] < 0.1) { status = ORACLE_STAGNATED; ++m; break; }
+    }
+    res->iterations = m;
+    res->status = status;
+    memcpy(D, X, sizeof(double) * (size_t)nn);
+    res->trace = trace_of(D, n);
+    free(X); free(S); free(e);
+    return status;
+}
+
+/*
+ * The same recursion on eigenvalues: x_i = (emax - lambda_i)/(emax - emin);
+ * tr = sum x_i; e = sqrt(sum (x_i^2 - x_i)^2); x_i <- 2x_i - x_i^2 or x_i^2.
+ * emin/emax are passed in so the caller can use the matrix's Gershgorin
+ * bounds.  x_out (length n, may be NULL) receives the final x_i.
+ */
+int oracle_sp2_spectral(const double* lambda, int n, int n_occ, double emin, double emax,
+                        double tol, int max_iter, double* x_out, oracle_sp2_result* res,
+                        double* tr_hist, double* e_hist)
+{
+    if (!res) return ORACLE_INVALID;
+    memset(res, 0, sizeof(*res));
+    if (n <= 0 || !lambda || n_occ < 0 || n_occ > n || !(tol > 0.0) || max_iter < 0) {
+        res->status = ORACLE_INVALID;
+        return ORACLE_INVALID;
+    }
+    res->emin = emin;
+    res->emax = emax;
+    if (n_occ == 0 || n_occ == n) {
+        if (x_out)
+            for (int i = 0; i < n; ++i) x_out[i] = (n_occ == n) ? 1.0 : 0.0;
+        res->trace = (double)n_occ;
+        res->status = ORACLE_OK;
+        return ORACLE_OK;
+    }
+    if (!(emax > emin)) { res->status = ORACLE_DEGENERATE; return ORACLE_DEGENERATE; }
+    double* x = (double*)malloc(sizeof(double) * (size_t)n);
+    double* e = (double*)malloc(sizeof(double) * (size_t)(max_iter > 0 ? max_iter : 1));
+    if (!x || !e) { free(x); free(e); res->status = ORACLE_NOMEM; return ORACLE_NOMEM; }
+    for (int i = 0; i < n; ++i) x[i] = (emax - lambda[i]) / (emax - emin);
+    int status = ORACLE_NOT_CONVERGED;
+    int m;
+    for (m = 0; m < max_iter; ++m) {
+        double tr = 0.0, e2 = 0.0;
+        for (int i = 0; i < n; ++i) tr += x[i];
+        for (int i = 0; i < n; ++i) {
+            double d = x[i] * x[i] - x[i];
+            e2 += d * d;
+        }
+        e[m] = sqrt(e2);
+        int grow = (tr - (double)n_occ <= 0.0);
+        for (int i = 0; i < n; ++i) {
+            double sq = x[i] * x[i];
+            x[i] = grow ? 2.0 * x[i] - sq : sq;
+        }
+        if (grow && m < 128) res->branch_mask[m / 64] |= (uint64_t)1 << (m % 64);
+        if (tr_hist) tr_hist[m] = tr;
+        if (e_hist) e_hist[m] = e[m];
+        res->idempotency = e[m];
+        if (e[m] <= tol) { status = ORACLE_OK; ++m; break; }
+        if (m >= 2 && e[m] >= e[m - 2] && e[m] < 0.1) { status = ORACLE_STAGNATED; ++m; break; }
+    }
+    res->iterations = m;
+    res->status = status;
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += x[i];
+    res->trace = t;
+    if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)n);
+    free(x); free(e);
+    return status;
+}
+
+/*
+ * Entries (I[t], J[t]) of one SP2 step applied to X (n x n, row-major):
+ * (X X)_ij if grow == 0, else 2 X_ij - (X X)_ij.  The sum over k runs in
+ * increasing k, as in the full product above.
+ */
+void oracle_sp2_step_entries(const double* X, int n, int grow, const int* I, const int* J,
+                             int count, double* out)
+{
+    for (int t = 0; t < count; ++t) {
+        int i = I[t], j = J[t];
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += X[(long)i * n + k] * X[(long)k * n + j];
+        out[t] = grow ? 2.0 * X[(long)i * n + j] - s : s;
+    }
+}

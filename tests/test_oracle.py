@@ -1,0 +1,241 @@
+"""Pins for the FP64 CPU oracle (no GPU).
+
+The oracle is checked against things other than itself: hand-derived closed
+forms (tests/golden), a third-party eigensolver (LAPACK through NumPy),
+exact invariants of projectors, brute force on diagonal inputs, and
+equivariances of the density matrix.  Each test names the plausible oracle
+mistake it would catch.
+"""
+import numpy as np
+import pytest
+
+import golden
+from tbgen import diagonal_hamiltonian, make_tb_hamiltonian, two_level_hamiltonian
+
+
+def fro_rms(A):
+    return np.linalg.norm(A) / np.sqrt(A.shape[0])
+
+
+def lapack_dm(H, n_occ):
+    w, V = np.linalg.eigh(H)
+    return V[:, :n_occ] @ V[:, :n_occ].T, w
+
+
+# --------------------------------------------------------------------------- bounds
+
+def test_gershgorin_hand_3x3(oracle_lib):
+    g = golden.load("gershgorin_3x3.txt")
+    lo, hi = oracle_lib.gershgorin(g["H"])
+    assert lo == g["emin"] and hi == g["emax"]          # catches a dropped |.| or a wrong row/col
+
+
+def test_gershgorin_symmetric_part(oracle_lib):
+    g = golden.load("gershgorin_nonsym_2x2.txt")
+    lo, hi = oracle_lib.gershgorin(g["H"])
+    assert (lo, hi) == (g["emin"], g["emax"])           # catches reading H instead of (H+H^T)/2
+    r = oracle_lib.sp2(g["H"], int(g["n_occ"]))
+    assert np.abs(r.D - g["D"]).max() < 1e-10
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gershgorin_contains_spectrum(oracle_lib, seed):
+    H = make_tb_hamiltonian(64, seed).H
+    lo, hi = oracle_lib.gershgorin(H)
+    w = np.linalg.eigvalsh(H)
+    assert lo <= w[0] and w[-1] <= hi
+    # exact for a diagonal matrix: the discs have radius 0
+    Hd = diagonal_hamiltonian(17, seed)
+    lo, hi = oracle_lib.gershgorin(Hd)
+    assert lo == np.diag(Hd).min() and hi == np.diag(Hd).max()
+
+
+def test_init_matches_hand_values(oracle_lib):
+    g = golden.load("dm_2x2_tie.txt")
+    X0 = oracle_lib.sp2_init(g["H"], g["emin"], g["emax"])
+    assert np.array_equal(X0, g["X0"])                   # catches a sign/shift error in D_0
+    assert np.trace(X0) == 1.0
+
+
+# --------------------------------------------------------------------------- Jacobi
+
+@pytest.mark.parametrize("n,seed", [(5, 0), (33, 1), (64, 2)])
+def test_jacobi_against_lapack(oracle_lib, n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    w, V, sweeps = oracle_lib.jacobi_eigh(A)
+    wl = np.linalg.eigvalsh(A)
+    scale = np.abs(wl).max()
+    assert np.abs(w - wl).max() <= 1e-13 * scale * n
+    assert np.abs(V.T @ V - np.eye(n)).max() < 1e-13 * n
+    assert np.abs(A @ V - V * w).max() < 1e-12 * scale * n
+    assert sweeps < 30
+
+
+def test_jacobi_dm_closed_form_2x2(oracle_lib):
+    g = golden.load("dm_2x2_tie.txt")
+    D, w, gap = oracle_lib.jacobi_dm(g["H"], 1)
+    assert np.abs(w - g["eigenvalues"]).max() < 1e-14
+    assert np.abs(D - g["D"]).max() < 1e-15
+    assert gap == pytest.approx(10.0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_jacobi_dm_random_2x2_closed_form(oracle_lib, seed):
+    rng = np.random.default_rng(100 + seed)
+    a, b, c = rng.normal(size=3) * [3, 2, 3]
+    H = np.array([[a, b], [b, c]])
+    lp = (a + c) / 2 + np.sqrt(((a - c) / 2) ** 2 + b * b)
+    lm = (a + c) / 2 - np.sqrt(((a - c) / 2) ** 2 + b * b)
+    Dexact = (lp * np.eye(2) - H) / (lp - lm)
+    D, _, _ = oracle_lib.jacobi_dm(H, 1)
+    assert np.abs(D - Dexact).max() < 1e-13
+    r = oracle_lib.sp2(H, 1)
+    assert r.status == 0
+    assert np.abs(r.D - Dexact).max() < 1e-10
+
+
+@pytest.mark.parametrize("n,seed", [(64, 3), (128, 4)])
+def test_jacobi_dm_matches_lapack_projector(oracle_lib, n, seed):
+    inst = make_tb_hamiltonian(n, seed)
+    D, w, gap = oracle_lib.jacobi_dm(inst.H, inst.n_occ)
+    Dl, wl = lapack_dm(inst.H, inst.n_occ)
+    assert fro_rms(D - Dl) < 1e-12
+    assert gap == pytest.approx(0.5, abs=1e-9)
+
+
+# --------------------------------------------------------------------------- SP2
+
+def test_tie_goes_to_grow_branch(oracle_lib):
+    """tr X0 == n_occ exactly: the listing's "<=" takes 2X - X^2 first."""
+    g = golden.load("dm_2x2_tie.txt")
+    r = oracle_lib.sp2(g["H"], 1, max_iter=1)
+    assert r.status == 1 and r.iterations == 1
+    assert r.branches() == [int(g["first_branch"])]
+    assert r.tr_hist[0] == 1.0
+    rs, x = oracle_lib.sp2_spectral(g["eigenvalues"], 1, g["emin"], g["emax"], max_iter=1)
+    assert rs.branches() == [1]
+    assert np.abs(x - g["x_after_first_step"]).max() < 1e-15
+    full = oracle_lib.sp2(g["H"], 1)
+    assert full.status == 0 and np.abs(full.D - g["D"]).max() < 1e-10
+
+
+@pytest.mark.parametrize("n,seed", [(32, 0), (64, 1), (128, 2), (256, 0)])
+def test_sp2_matches_jacobi_dm(oracle_lib, n, seed):
+    inst = make_tb_hamiltonian(n, seed)
+    D, w, gap = oracle_lib.jacobi_dm(inst.H, inst.n_occ)
+    r = oracle_lib.sp2(inst.H, inst.n_occ, tol=1e-10)
+    assert r.status == 0
+    assert 20 <= r.iterations <= 45
+    assert fro_rms(r.D - D) < 1e-10
+
+
+@pytest.mark.parametrize("n,seed", [(64, 5), (128, 6)])
+def test_sp2_invariants(oracle_lib, n, seed):
+    inst = make_tb_hamiltonian(n, seed)
+    H = inst.H
+    r = oracle_lib.sp2(H, inst.n_occ)
+    D = r.D
+    wl = np.linalg.eigvalsh(H)
+    assert np.abs(D - D.T).max() < 1e-13
+    assert np.linalg.norm(D @ D - D) < 1e-9
+    assert abs(np.trace(D) - inst.n_occ) < 1e-9
+    assert np.linalg.norm(H @ D - D @ H) / np.sqrt(n) < 1e-8
+    assert np.trace(D @ H) == pytest.approx(wl[: inst.n_occ].sum(), rel=1e-11)
+    wd = np.linalg.eigvalsh(D)
+    assert np.abs(wd[: n - inst.n_occ]).max() < 1e-9 and np.abs(wd[n - inst.n_occ:] - 1).max() < 1e-9
+
+
+@pytest.mark.parametrize("n,k", [(16, 5), (40, 20), (64, 9)])
+def test_two_level_system(oracle_lib, n, k):
+    H, P = two_level_hamiltonian(n, k, alpha=-1.3, beta=2.1, seed=n + k)
+    r = oracle_lib.sp2(H, k)
+    assert r.status == 0
+    assert np.abs(r.D - P).max() < 1e-9
+    D, _, _ = oracle_lib.jacobi_dm(H, k)
+    assert np.abs(D - P).max() < 1e-12
+    # the spectral recursion needs only the two levels with their multiplicities
+    lam = np.array([-1.3] * k + [2.1] * (n - k))
+    rs, _ = oracle_lib.sp2_spectral(lam, k, r.emin, r.emax)
+    assert rs.iterations == r.iterations
+
+
+@pytest.mark.parametrize("n,seed", [(7, 0), (31, 1), (100, 2)])
+def test_diagonal_brute_force_and_bitwise(oracle_lib, n, seed):
+    Hd = diagonal_hamiltonian(n, seed)
+    d = np.diag(Hd)
+    n_occ = n // 3 + 1
+    r = oracle_lib.sp2(Hd, n_occ)
+    assert r.status == 0
+    want = np.zeros(n)
+    want[np.argsort(d)[:n_occ]] = 1.0                    # brute force: the n_occ lowest levels
+    assert np.abs(np.diag(r.D) - want).max() < 1e-9
+    assert np.count_nonzero(r.D - np.diag(np.diag(r.D))) == 0
+    # SP2 acts entrywise on a diagonal matrix: the spectral recursion over the
+    # diagonal (same order, same bounds) must agree bit for bit
+    rs, x = oracle_lib.sp2_spectral(d, n_occ, r.emin, r.emax)
+    assert rs.iterations == r.iterations and rs.branch_mask == r.branch_mask
+    assert np.array_equal(x, np.diag(r.D))
+
+
+@pytest.mark.parametrize("n,seed", [(64, 7), (128, 8), (256, 9)])
+def test_spectral_predicts_matrix_steering(oracle_lib, n, seed):
+    inst = make_tb_hamiltonian(n, seed)
+    r = oracle_lib.sp2(inst.H, inst.n_occ)
+    w = np.linalg.eigvalsh(inst.H)
+    rs, _ = oracle_lib.sp2_spectral(w, inst.n_occ, r.emin, r.emax)
+    assert rs.iterations == r.iterations
+    trm, trs = np.asarray(r.tr_hist), np.asarray(rs.tr_hist)
+    assert np.abs(trm - trs).max() <= 1e-9 * n
+    decided = np.abs(trm - inst.n_occ) > 1e-9 * n
+    bm, bs = np.array(r.branches()), np.array(rs.branches())
+    assert np.array_equal(bm[decided], bs[decided])
+    assert np.abs(np.asarray(r.e_hist)[:-3] - np.asarray(rs.e_hist)[:-3]).max() < 1e-8
+
+
+def test_equivariances(oracle_lib):
+    inst = make_tb_hamiltonian(64, 11)
+    H, k = inst.H, inst.n_occ
+    D = oracle_lib.sp2(H, k).D
+    rng = np.random.default_rng(0)
+    p = rng.permutation(64)
+    Dp = oracle_lib.sp2(H[np.ix_(p, p)], k).D
+    assert np.abs(Dp - D[np.ix_(p, p)]).max() < 1e-9    # catches index mix-ups
+    assert np.abs(oracle_lib.sp2(H + 3.7 * np.eye(64), k).D - D).max() < 1e-9
+    assert np.abs(oracle_lib.sp2(2.5 * H, k).D - D).max() < 1e-9
+    Dph = oracle_lib.sp2(-H, 64 - k).D                   # particle-hole symmetry
+    assert np.abs(Dph - (np.eye(64) - D)).max() < 1e-9
+
+
+def test_special_and_error_cases(oracle_lib):
+    H = make_tb_hamiltonian(16, 3).H
+    r0 = oracle_lib.sp2(H, 0)
+    assert r0.status == 0 and r0.iterations == 0 and not r0.D.any()
+    rn = oracle_lib.sp2(H, 16)
+    assert rn.status == 0 and np.array_equal(rn.D, np.eye(16))
+    assert oracle_lib.sp2(2.0 * np.eye(8), 3).status == oracle_lib.DEGENERATE
+    Hn = H.copy()
+    Hn[3, 5] = np.nan
+    assert oracle_lib.sp2(Hn, 8).status == oracle_lib.INVALID
+    r1 = oracle_lib.sp2(H, 8, max_iter=1)
+    assert r1.status == oracle_lib.NOT_CONVERGED and r1.iterations == 1
+    # a tolerance below the rounding floor ends on the stagnation rule
+    rs = oracle_lib.sp2(H, 8, tol=1e-300)
+    assert rs.status == oracle_lib.STAGNATED
+    assert np.linalg.norm(rs.D @ rs.D - rs.D) < 1e-12
+    assert oracle_lib.sp2(H, 8, tol=0.0).status == oracle_lib.INVALID
+
+
+def test_step_entries_match_library_matmul(oracle_lib):
+    inst = make_tb_hamiltonian(48, 2)
+    lo, hi = oracle_lib.gershgorin(inst.H)
+    X = oracle_lib.sp2_init(inst.H, lo, hi)
+    rng = np.random.default_rng(1)
+    I = rng.integers(0, 48, 50)
+    J = rng.integers(0, 48, 50)
+    S = X @ X
+    for grow in (0, 1):
+        got = oracle_lib.sp2_step_entries(X, grow, I, J)
+        want = (2 * X - S if grow else S)[I, J]
+        assert np.abs(got - want).max() < 1e-14
