@@ -1,0 +1,201 @@
+// sp2_api.hip -- host side of libsp2.so: argument checks, workspace layout and
+// the stream-ordered launch sequence of one SP2 solve.  See include/sp2.h for
+// the contract of every entry point.
+//
+// Launch sequence of sp2_density (all on the caller's stream, no host round
+// trip inside the loop):
+//   reset state -> Gershgorin partial/final -> X_0 -> SYRK step x k ... -> copy to D
+// The SYRK steps are queued in chunks.  After each chunk the device "done"
+// flag is copied to pinned host memory behind an event; the host inspects the
+// flag of chunk c only after chunk c+1 is queued, so the GPU never waits for
+// the host.  Steps queued after convergence return at their first
+// instruction.
+#include <cmath>
+#include <cstring>
+
+#include "sp2_internal.h"
+
+using namespace sp2;
+
+namespace {
+
+constexpr int kMaxDevices = 16;
+
+// Per-thread, per-device pinned status buffer and events, made on first use
+// and kept until the thread ends.
+struct HostSlots {
+    int* flags = nullptr;     // 2 pinned ints
+    State* state = nullptr;   // pinned copy of the device state
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool ready = false;
+};
+
+thread_local HostSlots t_slots[kMaxDevices];
+
+hipError_t slots_for_current(HostSlots** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    HostSlots& s = t_slots[dev];
+    if (!s.ready) {
+        e = hipHostMalloc((void**)&s.flags, 2 * sizeof(int), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        e = hipHostMalloc((void**)&s.state, sizeof(State), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        for (int i = 0; i < 2; ++i) {
+            e = hipEventCreateWithFlags(&s.ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        s.ready = true;
+    }
+    *out = &s;
+    return hipSuccess;
+}
+
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+size_t elem_size(sp2_dtype dt) { return dt == SP2_F64 ? sizeof(double) : sizeof(float); }
+
+int fail(sp2_info* info, int code) {
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->status = code;
+    }
+    return code;
+}
+
+#define SP2_HIP(call)                                  \
+    do {                                               \
+        hipError_t _e = (call);                        \
+        if (_e != hipSuccess) return fail(info, SP2_E_HIP); \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int sp2_version(void) { return 100; }
+
+const char* sp2_status_str(int status) {
+    switch (status) {
+        case SP2_OK: return "converged";
+        case SP2_E_NOT_CONVERGED: return "not converged within max_iter";
+        case SP2_E_STAGNATED: return "stagnated at the rounding floor";
+        case SP2_E_FALLBACK: return "fell back to plain SP2";
+        case SP2_E_INVALID: return "invalid argument or non-finite input";
+        case SP2_E_DEGENERATE: return "degenerate spectrum (emax == emin)";
+        case SP2_E_WORKSPACE: return "workspace missing, too small or misaligned";
+        case SP2_E_HIP: return "HIP runtime error";
+        case SP2_E_UNSUPPORTED: return "compute mode not built";
+        default: return "unknown status";
+    }
+}
+
+size_t sp2_workspace_size(int n, sp2_dtype dtype, sp2_compute compute) {
+    if (n <= 0 || n > 65536) return 0;
+    if (dtype != SP2_F64 && dtype != SP2_F32) return 0;
+    if (compute != SP2_C_F64) return 0;
+    return make_layout(n).total;
+}
+
+int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, int max_iter,
+                sp2_dtype dtype, sp2_compute compute, int fp64_prefix_iters, void* workspace,
+                size_t workspace_bytes, void* hip_stream, sp2_info* info) {
+    (void)fp64_prefix_iters;
+    if (!H || !D || n <= 0 || n > 65536 || ld < n || n_occ < 0 || n_occ > n)
+        return fail(info, SP2_E_INVALID);
+    if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 0 || max_iter > SP2_MAX_ITER)
+        return fail(info, SP2_E_INVALID);
+    if (dtype != SP2_F64 && dtype != SP2_F32) return fail(info, SP2_E_INVALID);
+    if (compute < SP2_C_F64 || compute > SP2_C_FP8) return fail(info, SP2_E_INVALID);
+    if (compute != SP2_C_F64) return fail(info, SP2_E_UNSUPPORTED);
+    const Layout L = make_layout(n);
+    if (!workspace || workspace_bytes < L.total ||
+        (reinterpret_cast<uintptr_t>(workspace) % SP2_WORKSPACE_ALIGN) != 0)
+        return fail(info, SP2_E_WORKSPACE);
+    const size_t mbytes = ((size_t)(n - 1) * ld + n) * elem_size(dtype);
+    if (ranges_overlap(H, mbytes, D, mbytes) || ranges_overlap(D, mbytes, workspace, L.total))
+        return fail(info, SP2_E_INVALID);
+
+    hipStream_t s = (hipStream_t)hip_stream;
+    char* ws = (char*)workspace;
+    State* st = (State*)(ws + L.off_state);
+    double* part = (double*)(ws + L.off_part);
+    double* rowpart = (double*)(ws + L.off_rowpart);
+    double* x0 = (double*)(ws + L.off_x0);
+    double* x1 = (double*)(ws + L.off_x1);
+
+    HostSlots* hs = nullptr;
+    SP2_HIP(slots_for_current(&hs));
+
+    SP2_HIP(launch_reset(st, n, n_occ, tol, max_iter, s));
+    SP2_HIP(launch_bounds(H, dtype, n, ld, L, st, rowpart, part, s));
+    SP2_HIP(launch_init(H, dtype, n, ld, L, st, x0, part, s));
+
+    const int chunk = L.ldp >= 2048 ? 4 : 8;
+    int issued = 0, pending = -1, slot = 0;
+    bool stop = false;
+    while (issued < max_iter && !stop) {
+        const int c = (max_iter - issued) < chunk ? (max_iter - issued) : chunk;
+        for (int i = 0; i < c; ++i, ++issued) {
+            const double* xc = (issued & 1) ? x1 : x0;
+            double* xn = (issued & 1) ? x0 : x1;
+            SP2_HIP(launch_syrk_f64(L, xc, xn, st, part, s));
+        }
+        SP2_HIP(hipMemcpyAsync(&hs->flags[slot], &st->done, sizeof(int), hipMemcpyDeviceToHost, s));
+        SP2_HIP(hipEventRecord(hs->ev[slot], s));
+        if (pending >= 0) {
+            SP2_HIP(hipEventSynchronize(hs->ev[pending]));
+            if (hs->flags[pending]) stop = true;
+        }
+        pending = slot;
+        slot ^= 1;
+    }
+    SP2_HIP(launch_finalize(D, dtype, n, ld, L, st, x0, x1, s));
+    SP2_HIP(hipMemcpyAsync(hs->state, st, sizeof(State), hipMemcpyDeviceToHost, s));
+    SP2_HIP(hipStreamSynchronize(s));
+
+    const State& h = *hs->state;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->status = h.status;
+        info->iterations = h.iterations;
+        info->fp64_prefix_iters = h.fp64_steps;
+        info->refine_steps = 0;
+        info->trace = h.tr;
+        info->trace_error = std::fabs(h.tr - (double)n_occ);
+        info->idempotency = h.idem;
+        info->emin = h.emin;
+        info->emax = h.emax;
+        info->branch_mask[0] = h.branch_mask[0];
+        info->branch_mask[1] = h.branch_mask[1];
+    }
+    return h.status;
+}
+
+int sp2_history(const void* workspace, int count, double* tr_hist, double* e_hist,
+                void* hip_stream) {
+    sp2_info* info = nullptr;
+    if (!workspace || count < 0) return SP2_E_INVALID;
+    if ((reinterpret_cast<uintptr_t>(workspace) % SP2_WORKSPACE_ALIGN) != 0) return SP2_E_WORKSPACE;
+    HostSlots* hs = nullptr;
+    SP2_HIP(slots_for_current(&hs));
+    hipStream_t s = (hipStream_t)hip_stream;
+    SP2_HIP(hipMemcpyAsync(hs->state, workspace, sizeof(State), hipMemcpyDeviceToHost, s));
+    SP2_HIP(hipStreamSynchronize(s));
+    const State& h = *hs->state;
+    int m = h.iterations < count ? h.iterations : count;
+    if (m > SP2_MAX_ITER) m = SP2_MAX_ITER;
+    for (int i = 0; i < m; ++i) {
+        if (tr_hist) tr_hist[i] = h.tr_hist[i];
+        if (e_hist) e_hist[i] = h.e_hist[i];
+    }
+    return m;
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// sp2_internal.h -- device-side loop state, workspace layout and helpers shared by
+// the gfx950 kernels and the host driver of libsp2.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sp2.h"
+
+namespace sp2 {
+
+constexpr int kThreads = 256;        // every kernel uses 4 wave64s per workgroup
+constexpr int kBndTile = 64;         // tile edge of the bounds / init / finalize kernels
+constexpr int kBndColsPerBlock = 512;
+
+// Loop state, resident in the workspace.  Written by the last-arriving block
+// of each kernel; read by every kernel at start (kernel boundaries order it).
+struct State {
+    double emin, emax;
+    double tr;          // trace of the current iterate X_m
+    double fro2;        // ||X_m||_F^2
+    double idem;        // e of the last step
+    double tol;
+    double nocc;
+    int32_t n, max_iter;
+    int32_t grow;       // 1 when the next step takes 2X - X^2
+    int32_t done;
+    int32_t status;
+    int32_t iterations; // squarings done; X_m lives in buffer (m & 1)
+    int32_t special;    // 1: n_occ == 0 -> D = 0; 2: n_occ == n -> D = I
+    int32_t bad;        // a non-finite entry was seen in H
+    uint32_t ticket;    // arrival counter of the last-block reductions
+    int32_t fp64_steps;
+    uint64_t branch_mask[2];
+    double tr_hist[SP2_MAX_ITER];
+    double e_hist[SP2_MAX_ITER];
+};
+
+// Workspace layout (byte offsets from the 256-byte aligned base).
+struct Layout {
+    int n, ldp, bt;          // padded edge, SYRK tile edge
+    int tiles;               // lower tiles of the SYRK grid
+    size_t off_state, off_part, off_rowpart, off_x0, off_x1, total;
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// SYRK tile edge for an n x n problem.
+inline int syrk_tile(int n) { return n <= 2048 ? 64 : 128; }
+
+inline Layout make_layout(int n) {
+    Layout L{};
+    L.n = n;
+    L.bt = syrk_tile(n);
+    L.ldp = (int)align_up((size_t)n, (size_t)L.bt);
+    int T = L.ldp / L.bt;
+    L.tiles = T * (T + 1) / 2;
+    int nb = L.ldp / kBndTile;
+    size_t part_entries = (size_t)L.tiles * 4;
+    size_t init_entries = (size_t)nb * nb * 4;
+    if (init_entries > part_entries) part_entries = init_entries;
+    int nsplit = (n + kBndColsPerBlock - 1) / kBndColsPerBlock;
+    size_t off = 0;
+    L.off_state = off;   off = align_up(off + sizeof(State), 256);
+    L.off_part = off;    off = align_up(off + part_entries * sizeof(double), 256);
+    L.off_rowpart = off; off = align_up(off + ((size_t)nsplit * L.ldp + 2 * (size_t)L.ldp) * sizeof(double), 256);
+    L.off_x0 = off;      off = align_up(off + (size_t)L.ldp * L.ldp * sizeof(double), 256);
+    L.off_x1 = off;      off = align_up(off + (size_t)L.ldp * L.ldp * sizeof(double), 256);
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------- device helpers
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sum of v over the 256 threads in a fixed order (wave sums, then waves 0..3).
+// `scratch` holds at least 4 doubles of LDS.  Result valid in every thread.
+__device__ inline double block_sum(double v, double* scratch) {
+    v = wave_sum(v);
+    int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    double r = ((scratch[0] + scratch[1]) + scratch[2]) + scratch[3];
+    __syncthreads();
+    return r;
+}
+
+// Called by every thread after this block's partial results are stored.
+// Returns true in every thread of the single block that arrives last; that
+// block then sees all other blocks' partials.
+__device__ inline bool arrive_last(State* st, unsigned nblocks, int* flag_lds) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = atomicAdd(&st->ticket, 1u);
+        *flag_lds = (t == nblocks - 1);
+    }
+    __syncthreads();
+    bool last = *flag_lds != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// ---------------------------------------------------------------- host launchers
+
+hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, hipStream_t s);
+hipError_t launch_bounds(const void* H, sp2_dtype dt, int n, int ld, const Layout& L, State* st,
+                         double* rowpart, double* part, hipStream_t s);
+hipError_t launch_init(const void* H, sp2_dtype dt, int n, int ld, const Layout& L, State* st,
+                       double* x0, double* part, hipStream_t s);
+hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* st, double* part,
+                           hipStream_t s);
+hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, const State* st,
+                           const double* x0, const double* x1, hipStream_t s);
+
+}  // namespace sp2

@@ -136,3 +136,24 @@ def two_level_hamiltonian(n: int, k: int, alpha: float, beta: float, seed: int):
     H = alpha * P + beta * (np.eye(n) - P)
     H = 0.5 * (H + H.T)
     return H, P
+
+
+def gapped_random_hamiltonian(n: int, n_occ: int, gap: float, seed: int, spread: float = 10.0):
+    """Dense symmetric H = Q diag(eps) Q^T with a prescribed gap at n_occ.
+
+    eps: n_occ levels uniform in [-spread, -gap/2] and n - n_occ levels
+    uniform in [gap/2, spread], with the two innermost levels placed exactly at
+    -gap/2 and +gap/2 (so the HOMO-LUMO gap equals `gap`).  Works for any n
+    (the tight-binding model needs a multiple of 4).  Returns (H, eps sorted).
+    """
+    rng = np.random.default_rng(seed)
+    lo = rng.uniform(-spread, -gap / 2, size=n_occ)
+    hi = rng.uniform(gap / 2, spread, size=n - n_occ)
+    if n_occ > 0:
+        lo[np.argmax(lo)] = -gap / 2
+    if n - n_occ > 0:
+        hi[np.argmin(hi)] = gap / 2
+    eps = np.sort(np.concatenate([lo, hi]))
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * eps) @ Q.T
+    return np.ascontiguousarray(0.5 * (A + A.T)), eps
