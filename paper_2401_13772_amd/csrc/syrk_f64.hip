@@ -139,42 +139,34 @@ __global__ __launch_bounds__(kThreads, 1) void k_syrk_f64(const double* __restri
     }
 
     // ---------------- fused SP2 epilogue
-    // Accumulator layout of a 16x16 f64 block: lane l holds rows 4*(l/16)+r,
-    // r = 0..3, of column l%16.
+    // Accumulator layout of v_mfma_f64_16x16x4f64 (checked on gfx950): lane l
+    // holds column l%16 of the 16x16 block at rows l/16 + 4r, r = 0..3.
+    // For a fixed r the 64 lanes cover 4 rows x 16 consecutive columns, so the
+    // direct reads/writes are 128-byte row segments.
     double e2 = 0.0, trp = 0.0, fro = 0.0;
 #pragma unroll
     for (int mi = 0; mi < MI; ++mi) {
 #pragma unroll
         for (int ni = 0; ni < MI; ++ni) {
-            const int gi0 = ti * BT + wm * WT + mi * 16 + 4 * (lane >> 4);
+            const int gi0 = ti * BT + wm * WT + mi * 16 + (lane >> 4);
             const int gj = tj * BT + wn * WT + ni * 16 + (lane & 15);
-            // X is stored bitwise symmetric: X[gi][gj] == X[gj][gi]
-            const d4 xv = *(const d4*)(X + (size_t)gj * ldp + gi0);
-            d4 yn;
+            double xv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xv[r] = X[(size_t)(gi0 + 4 * r) * ldp + gj];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                const int gi = gi0 + 4 * r;
                 const double s = acc[mi][ni][r];
                 const double x = xv[r];
                 const double d = s - x;
                 const double xn = grow ? (2.0 * x - s) : s;
-                yn[r] = xn;
-                const int gi = gi0 + r;
                 const double wgt = (gi > gj) ? 2.0 : ((gi == gj) ? 1.0 : 0.0);
                 e2 += wgt * (d * d);
                 fro += wgt * (xn * xn);
                 if (gi == gj) trp += xn;
-            }
-            if (!diag) {
-                *(d4*)(Y + (size_t)gj * ldp + gi0) = yn;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Y[(size_t)(gi0 + r) * ldp + gj] = yn[r];
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int gi = gi0 + r;
-                    if (gi >= gj) Y[(size_t)gi * ldp + gj] = yn[r];
-                    if (gi > gj) Y[(size_t)gj * ldp + gi] = yn[r];
-                }
+                // lower copy; the upper copy mirrors it (diagonal tiles: lower half wins)
+                if (!diag || gi >= gj) Y[(size_t)gi * ldp + gj] = xn;
+                if (!diag || gi > gj) Y[(size_t)gj * ldp + gi] = xn;
             }
         }
     }
