@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""SP2 density-matrix throughput on one MI355X.
+
+One "step" is one complete SP2 solve of a synthetic tight-binding Hamiltonian
+through the C ABI: Gershgorin bounds, X_0, every trace-steered squaring until
+||X^2 - X||_F <= tol, and the copy of D.  Inputs are resident in HBM before
+the timed region starts.
+
+Default workload: n = 4096 (1024 atoms x 4 orbitals), n_occ = 2048, HOMO-LUMO
+gap opened to 0.5 eV, H stored in FP32, tol 1e-10.
+
+Printed (one JSON line on stdout): density matrices per second, algorithmic
+TFLOP/s (n^2 (n+1) per symmetric squaring), accuracy against an FP64
+eigendecomposition of the same stored H, the roofline position of the
+squaring kernel from HIP events taken around each of its launches inside the
+timed region, and the FP64 CPU oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SP2 density matrices/s + MFMA TFLOP/s at ‖D−D_ref‖_F/√n ≤ 1e-6 vs FP64 SP2"
+PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "fp8": 5000.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_sha(name):
+    path = os.path.join(ROOT, "paper_2401_13772_amd", "csrc", name)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(kernel_file, workload):
+    """HBM bytes per launch from a committed counter summary, if it is current.
+
+    The summary's lines `source_sha:`, `workload:`, `fetch_bytes_per_launch:` and
+    `write_bytes_per_launch:` are used only when source_sha matches the kernel
+    source as it is now.
+    """
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip().strip("-* `")] = v.strip().strip("` ")
+    if vals.get("source_sha") != kernel_sha(kernel_file):
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(H64, n_occ, iterations, steps):
+    """The FP64 oracle's SP2 loop on this host, `steps` squarings of the same
+    workload, scaled to density matrices per second with the GPU's iteration
+    count."""
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    threads = min(threads, oracle.max_threads()) if oracle.max_threads() > 0 else threads
+    t0 = time.perf_counter()
+    r = oracle.sp2(H64, n_occ, tol=1e-10, max_iter=steps, nthreads=threads)
+    dt = time.perf_counter() - t0
+    per_step = dt / max(r.iterations, 1)
+    return {
+        "value": 1.0 / (per_step * iterations),
+        "unit": "DM/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle_sp2 (plain C triple loops, FP64, OpenMP over rows) ran the first "
+                   f"{r.iterations} of {iterations} squarings of the same n={H64.shape[0]} solve "
+                   f"in {dt:.2f} s; value = 1/({per_step:.3f} s x {iterations})"),
+    }
+
+
+def copy_calibration(nbytes):
+    """A plain device-to-device copy of known size, for scaling HBM counters."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--gap", type=float, default=0.5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--compute", default="f64")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--cpu-steps", type=int, default=1,
+                    help="oracle squarings in the CPU-baseline sample (0 = skip)")
+    ap.add_argument("--no-reference", action="store_true",
+                    help="skip the FP64 eigendecomposition accuracy check (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy of BYTES bytes (counter scaling) and exit")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+
+    import paper_2401_13772_amd as sp2
+    from tbgen import make_tb_hamiltonian
+
+    n = args.n
+    n_occ = n // 2
+    storage = np.float32 if args.storage == "f32" else np.float64
+    log(f"generating tight-binding H n={n} seed={args.seed} gap={args.gap} storage={args.storage}")
+    t0 = time.perf_counter()
+    inst = make_tb_hamiltonian(n, args.seed, gap=args.gap, dtype=storage)
+    log(f"  generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    H = torch.from_numpy(inst.H).to(dev)
+    D = torch.empty_like(H)
+    ws = sp2.alloc_workspace(n, args.storage, args.compute, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def solve():
+        _, info = sp2.sp2_density(H, n_occ, tol=args.tol, max_iter=sp2.MAX_ITER,
+                                  compute=args.compute, D=D, workspace=ws, stream=stream)
+        if info.status < 0:
+            raise RuntimeError(f"sp2_density: {info.status_str}")
+        return info
+
+    log(f"warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        info = solve()
+    torch.cuda.synchronize()
+
+    log(f"timed x{args.steps}")
+    sp2.sp2_profile_enable(True)
+    kern_ms, kern_launches = 0.0, 0
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(solve())
+        ms, k = sp2.sp2_profile_read()
+        kern_ms += ms
+        kern_launches += k
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sp2.sp2_profile_enable(False)
+    info = infos[-1]
+    iters = info.iterations
+    ms_per_step = 1e3 * elapsed / args.steps
+    dms = args.steps / elapsed
+    flops_per_sq = float(n) * n * (n + 1)
+    flops_per_dm = sum(i.iterations for i in infos) / len(infos) * flops_per_sq
+    tflops = flops_per_dm * dms / 1e12
+    avg_launch_s = kern_ms / 1e3 / max(kern_launches, 1)
+    achieved = flops_per_sq / avg_launch_s / 1e12
+    log(f"status={info.status_str} iterations={iters} {ms_per_step:.3f} ms/DM "
+        f"{dms:.2f} DM/s {tflops:.2f} TFLOP/s; squaring kernel {1e3 * avg_launch_s:.3f} ms "
+        f"-> {achieved:.2f} TFLOP/s")
+
+    # accuracy of the last D
+    Dg = D.double()
+    Hd = H.double()
+    idem = float(torch.linalg.norm(Dg @ Dg - Dg))
+    comm = float(torch.linalg.norm(Hd @ Dg - Dg @ Hd)) / np.sqrt(n)
+    tr_err = abs(float(torch.trace(Dg)) - n_occ)
+    err_ref = None
+    if not args.no_reference:
+        log("FP64 eigendecomposition of the stored H (accuracy reference)")
+        t0 = time.perf_counter()
+        w, V = np.linalg.eigh(inst.H.astype(np.float64))
+        Dref = torch.from_numpy(V[:, :n_occ] @ V[:, :n_occ].T).to(dev)
+        err_ref = float(torch.linalg.norm(Dg - Dref)) / np.sqrt(n)
+        log(f"  eigh {time.perf_counter() - t0:.1f} s; rms|D - D_ref| = {err_ref:.3e}")
+        del Dref
+
+    dtype_name = {"f64": "f64"}.get(args.compute, args.compute)
+    peak = PEAKS_TFLOPS["f64"] if args.compute == "f64" else None
+    kernel_file = "syrk_f64.hip"
+    workload = f"sp2_tb_n{n}_{args.storage}storage_{args.compute}"
+    traffic = read_traffic(kernel_file, workload)
+    roofline = {
+        "kernel": "k_syrk_f64",
+        "bound": "mfma",
+        "achieved": round(achieved, 3),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4) if peak else None,
+        "traffic": traffic,
+        "per_launch_flops": flops_per_sq,
+        "avg_launch_ms": round(1e3 * avg_launch_s, 4),
+        "launches_timed": kern_launches,
+    }
+
+    cpu = None
+    if args.cpu_steps > 0:
+        log(f"CPU oracle sample: {args.cpu_steps} squarings")
+        cpu = cpu_baseline(inst.H.astype(np.float64), n_occ, iters, args.cpu_steps)
+        log(f"  {cpu['sample']}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(dms, 4),
+        "unit": "DM/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_name,
+        "data": "synthetic",
+        "config": {"workload": workload, "n": n, "n_occ": n_occ, "gap_eV": args.gap,
+                   "storage": args.storage, "compute": args.compute, "tol": args.tol,
+                   "seed": args.seed},
+        "tflops_algorithmic": round(tflops, 3),
+        "iterations": iters,
+        "status": info.status_str,
+        "err_rms_vs_fp64_eigh": err_ref,
+        "idempotency_fro": idem,
+        "trace_error": tr_err,
+        "commutator_rms": comm,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,17 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
 int sp2_history(const void* workspace, int count, double* tr_hist, double* e_hist,
                 void* hip_stream);
 
+/*
+ * Kernel timing for measurement (not part of the method).  With
+ * sp2_profile_enable(1), later sp2_density calls on this thread and device
+ * record a HIP event pair around every squaring-kernel launch on the call's
+ * stream; sp2_profile_read then returns the summed event time of the real
+ * (not skipped) squarings of the last call and their number.  Host pointers;
+ * either may be NULL.  Returns SP2_OK or SP2_E_HIP.
+ */
+int sp2_profile_enable(int on);
+int sp2_profile_read(double* step_ms_total, int* steps);
+
 #ifdef __cplusplus
 }
 #endif

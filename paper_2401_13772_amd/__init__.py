@@ -56,6 +56,10 @@ _lib.sp2_density.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
 _lib.sp2_history.restype = ctypes.c_int
 _lib.sp2_history.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double), _vp]
+_lib.sp2_profile_enable.restype = ctypes.c_int
+_lib.sp2_profile_enable.argtypes = [ctypes.c_int]
+_lib.sp2_profile_read.restype = ctypes.c_int
+_lib.sp2_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
 
 
 @dataclass
@@ -169,6 +173,23 @@ def sp2_history(workspace, count: int = MAX_ITER, stream=None):
     return np.array(tr[:m]), np.array(e[:m])
 
 
+def sp2_profile_enable(on: bool = True) -> None:
+    st = _lib.sp2_profile_enable(1 if on else 0)
+    if st != OK:
+        raise RuntimeError(f"sp2_profile_enable failed: {sp2_status_str(st)}")
+
+
+def sp2_profile_read():
+    """(summed squaring-kernel ms, number of squarings) of the last timed call."""
+    ms = ctypes.c_double()
+    steps = ctypes.c_int()
+    st = _lib.sp2_profile_read(ctypes.byref(ms), ctypes.byref(steps))
+    if st != OK:
+        raise RuntimeError(f"sp2_profile_read failed: {sp2_status_str(st)}")
+    return ms.value, steps.value
+
+
 def exported_symbols():
     """Names of the C entry points this binding wraps."""
-    return ["sp2_version", "sp2_status_str", "sp2_workspace_size", "sp2_density", "sp2_history"]
+    return ["sp2_version", "sp2_status_str", "sp2_workspace_size", "sp2_density", "sp2_history",
+            "sp2_profile_enable", "sp2_profile_read"]

@@ -17,7 +17,9 @@
 
 namespace sp2 {
 
-__global__ void k_reset(State* st, int n, int n_occ, double tol, int max_iter) {
+__global__ void k_reset(State* st, int n, int n_occ, double tol, int max_iter, unsigned* cnt,
+                        int ncnt) {
+    for (int i = threadIdx.x; i < ncnt; i += blockDim.x) cnt[i] = 0u;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->emin = 0.0;
     st->emax = 0.0;
@@ -241,8 +243,9 @@ __global__ __launch_bounds__(kThreads) void k_finalize(T* __restrict__ D, int n,
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, st, n, n_occ, tol, max_iter);
+hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, unsigned* cnt,
+                        int ncnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, st, n, n_occ, tol, max_iter, cnt, ncnt);
     return hipGetLastError();
 }
 

@@ -32,6 +32,35 @@ struct HostSlots {
 
 thread_local HostSlots t_slots[kMaxDevices];
 
+// Optional per-step kernel timing (sp2_profile_enable): an event pair around
+// every SYRK launch on the caller's stream.
+struct Profile {
+    bool on = false;
+    bool made = false;
+    hipEvent_t ev[2 * SP2_MAX_ITER];
+    double last_ms = 0.0;
+    int last_steps = 0;
+};
+
+thread_local Profile t_prof[kMaxDevices];
+
+hipError_t profile_for_current(Profile** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    Profile& p = t_prof[dev];
+    if (p.on && !p.made) {
+        for (int i = 0; i < 2 * SP2_MAX_ITER; ++i) {
+            e = hipEventCreate(&p.ev[i]);
+            if (e != hipSuccess) return e;
+        }
+        p.made = true;
+    }
+    *out = &p;
+    return hipSuccess;
+}
+
 hipError_t slots_for_current(HostSlots** out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -129,11 +158,16 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
     double* rowpart = (double*)(ws + L.off_rowpart);
     double* x0 = (double*)(ws + L.off_x0);
     double* x1 = (double*)(ws + L.off_x1);
+    unsigned* cnt = (unsigned*)(ws + L.off_cnt);
+    double* scratch = (double*)(ws + L.off_scratch);
 
     HostSlots* hs = nullptr;
     SP2_HIP(slots_for_current(&hs));
+    Profile* prof = nullptr;
+    SP2_HIP(profile_for_current(&prof));
+    const bool timed = prof->on;
 
-    SP2_HIP(launch_reset(st, n, n_occ, tol, max_iter, s));
+    SP2_HIP(launch_reset(st, n, n_occ, tol, max_iter, cnt, L.max_groups + 2, s));
     SP2_HIP(launch_bounds(H, dtype, n, ld, L, st, rowpart, part, s));
     SP2_HIP(launch_init(H, dtype, n, ld, L, st, x0, part, s));
 
@@ -145,7 +179,9 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
         for (int i = 0; i < c; ++i, ++issued) {
             const double* xc = (issued & 1) ? x1 : x0;
             double* xn = (issued & 1) ? x0 : x1;
-            SP2_HIP(launch_syrk_f64(L, xc, xn, st, part, s));
+            if (timed) SP2_HIP(hipEventRecord(prof->ev[2 * issued], s));
+            SP2_HIP(launch_syrk_f64(L, xc, xn, st, part, scratch, cnt, s));
+            if (timed) SP2_HIP(hipEventRecord(prof->ev[2 * issued + 1], s));
         }
         SP2_HIP(hipMemcpyAsync(&hs->flags[slot], &st->done, sizeof(int), hipMemcpyDeviceToHost, s));
         SP2_HIP(hipEventRecord(hs->ev[slot], s));
@@ -161,6 +197,16 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
     SP2_HIP(hipStreamSynchronize(s));
 
     const State& h = *hs->state;
+    if (timed) {
+        double total = 0.0;
+        for (int i = 0; i < h.iterations && i < issued; ++i) {
+            float ms = 0.f;
+            SP2_HIP(hipEventElapsedTime(&ms, prof->ev[2 * i], prof->ev[2 * i + 1]));
+            total += ms;
+        }
+        prof->last_ms = total;
+        prof->last_steps = h.iterations < issued ? h.iterations : issued;
+    }
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->status = h.status;
@@ -176,6 +222,21 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
         info->branch_mask[1] = h.branch_mask[1];
     }
     return h.status;
+}
+
+int sp2_profile_enable(int on) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SP2_E_HIP;
+    t_prof[dev].on = (on != 0);
+    return SP2_OK;
+}
+
+int sp2_profile_read(double* step_ms_total, int* steps) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SP2_E_HIP;
+    if (step_ms_total) *step_ms_total = t_prof[dev].last_ms;
+    if (steps) *steps = t_prof[dev].last_steps;
+    return SP2_OK;
 }
 
 int sp2_history(const void* workspace, int count, double* tr_hist, double* e_hist,

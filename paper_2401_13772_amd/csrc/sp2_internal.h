@@ -12,6 +12,7 @@ namespace sp2 {
 constexpr int kThreads = 256;        // every kernel uses 4 wave64s per workgroup
 constexpr int kBndTile = 64;         // tile edge of the bounds / init / finalize kernels
 constexpr int kBndColsPerBlock = 512;
+constexpr int kMaxPersistent = 1024; // upper bound on the stream-K grid
 
 // Loop state, resident in the workspace.  Written by the last-arriving block
 // of each kernel; read by every kernel at start (kernel boundaries order it).
@@ -40,7 +41,8 @@ struct State {
 struct Layout {
     int n, ldp, bt;          // padded edge, SYRK tile edge
     int tiles;               // lower tiles of the SYRK grid
-    size_t off_state, off_part, off_rowpart, off_x0, off_x1, total;
+    int max_groups;          // stream-K grid bound: min(tiles, kMaxPersistent)
+    size_t off_state, off_part, off_rowpart, off_cnt, off_scratch, off_x0, off_x1, total;
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -60,10 +62,13 @@ inline Layout make_layout(int n) {
     size_t init_entries = (size_t)nb * nb * 4;
     if (init_entries > part_entries) part_entries = init_entries;
     int nsplit = (n + kBndColsPerBlock - 1) / kBndColsPerBlock;
+    L.max_groups = L.tiles < kMaxPersistent ? L.tiles : kMaxPersistent;
     size_t off = 0;
     L.off_state = off;   off = align_up(off + sizeof(State), 256);
     L.off_part = off;    off = align_up(off + part_entries * sizeof(double), 256);
     L.off_rowpart = off; off = align_up(off + ((size_t)nsplit * L.ldp + 2 * (size_t)L.ldp) * sizeof(double), 256);
+    L.off_cnt = off;     off = align_up(off + (size_t)(L.max_groups + 2) * sizeof(unsigned), 256);
+    L.off_scratch = off; off = align_up(off + 2 * (size_t)(L.max_groups + 1) * L.bt * L.bt * sizeof(double), 256);
     L.off_x0 = off;      off = align_up(off + (size_t)L.ldp * L.ldp * sizeof(double), 256);
     L.off_x1 = off;      off = align_up(off + (size_t)L.ldp * L.ldp * sizeof(double), 256);
     L.total = off;
@@ -121,13 +126,14 @@ __device__ inline bool arrive_last(State* st, unsigned nblocks, int* flag_lds) {
 
 // ---------------------------------------------------------------- host launchers
 
-hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, hipStream_t s);
+hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, unsigned* cnt,
+                        int ncnt, hipStream_t s);
 hipError_t launch_bounds(const void* H, sp2_dtype dt, int n, int ld, const Layout& L, State* st,
                          double* rowpart, double* part, hipStream_t s);
 hipError_t launch_init(const void* H, sp2_dtype dt, int n, int ld, const Layout& L, State* st,
                        double* x0, double* part, hipStream_t s);
 hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* st, double* part,
-                           hipStream_t s);
+                           double* scratch, unsigned* cnt, hipStream_t s);
 hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, const State* st,
                            const double* x0, const double* x1, hipStream_t s);
 
