@@ -110,7 +110,9 @@ def main():
     ap.add_argument("--gap", type=float, default=0.5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--compute", default="f64")
+    ap.add_argument("--compute", default="f64", choices=["f64", "f16x2", "bf16x3", "bf16x2"])
+    ap.add_argument("--prefix", type=int, default=-1,
+                    help="FP64 steps before the split-operand phase (-1 = library default)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
     ap.add_argument("--cpu-steps", type=int, default=1,
                     help="oracle squarings in the CPU-baseline sample (0 = skip)")
@@ -151,7 +153,8 @@ def main():
 
     def solve():
         _, info = sp2.sp2_density(H, n_occ, tol=args.tol, max_iter=sp2.MAX_ITER,
-                                  compute=args.compute, D=D, workspace=ws, stream=stream)
+                                  compute=args.compute, fp64_prefix_iters=args.prefix, D=D,
+                                  workspace=ws, stream=stream)
         if info.status < 0:
             raise RuntimeError(f"sp2_density: {info.status_str}")
         return info
@@ -163,15 +166,17 @@ def main():
 
     log(f"timed x{args.steps}")
     sp2.sp2_profile_enable(True)
-    kern_ms, kern_launches = 0.0, 0
+    kern = {"f64": [0.0, 0], "split": [0.0, 0]}
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         infos.append(solve())
-        ms, k = sp2.sp2_profile_read()
-        kern_ms += ms
-        kern_launches += k
+        (fm, fk), (lm, lk) = sp2.sp2_profile_read_split()
+        kern["f64"][0] += fm
+        kern["f64"][1] += fk
+        kern["split"][0] += lm
+        kern["split"][1] += lk
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     sp2.sp2_profile_enable(False)
@@ -182,11 +187,39 @@ def main():
     flops_per_sq = float(n) * n * (n + 1)
     flops_per_dm = sum(i.iterations for i in infos) / len(infos) * flops_per_sq
     tflops = flops_per_dm * dms / 1e12
-    avg_launch_s = kern_ms / 1e3 / max(kern_launches, 1)
-    achieved = flops_per_sq / avg_launch_s / 1e12
-    log(f"status={info.status_str} iterations={iters} {ms_per_step:.3f} ms/DM "
-        f"{dms:.2f} DM/s {tflops:.2f} TFLOP/s; squaring kernel {1e3 * avg_launch_s:.3f} ms "
-        f"-> {achieved:.2f} TFLOP/s")
+    products = {"f64": 1, "f16x2": 3, "bf16x3": 6, "bf16x2": 3}[args.compute]
+    kinds = {
+        "f64": ("k_syrk_f64", PEAKS_TFLOPS["f64"], 1),
+        "split": ("k_syrk_lp", PEAKS_TFLOPS["bf16"], products),
+    }
+    lines = {}
+    for key, (ms_tot, launches) in kern.items():
+        if launches == 0:
+            continue
+        name, peak, mult = kinds[key]
+        avg_s = ms_tot / 1e3 / launches
+        ach = flops_per_sq / avg_s / 1e12
+        lines[key] = {
+            "kernel": name,
+            "bound": "mfma",
+            "achieved": round(ach, 3),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(ach / peak, 4),
+            "executed_tflops": round(ach * mult, 3),
+            "frac_executed": round(ach * mult / peak, 4),
+            "per_launch_flops": flops_per_sq,
+            "avg_launch_ms": round(1e3 * avg_s, 4),
+            "launches_timed": launches,
+            "share_of_solve": round(ms_tot / (1e3 * elapsed), 4),
+        }
+    dominant = max(lines, key=lambda k: kern[k][0])
+    log(f"status={info.status_str} iterations={iters} (FP64 prefix {info.fp64_prefix_iters}, "
+        f"refine {info.refine_steps}) {ms_per_step:.3f} ms/DM {dms:.2f} DM/s {tflops:.2f} TFLOP/s")
+    for key, ln in lines.items():
+        log(f"  {ln['kernel']}: {ln['launches_timed']} launches, {ln['avg_launch_ms']:.4f} ms avg, "
+            f"{ln['achieved']:.1f} TFLOP/s algorithmic ({ln['executed_tflops']:.1f} executed), "
+            f"{100 * ln['share_of_solve']:.1f}% of the solve")
 
     # accuracy of the last D
     Dg = D.double()
@@ -204,23 +237,12 @@ def main():
         log(f"  eigh {time.perf_counter() - t0:.1f} s; rms|D - D_ref| = {err_ref:.3e}")
         del Dref
 
-    dtype_name = {"f64": "f64"}.get(args.compute, args.compute)
-    peak = PEAKS_TFLOPS["f64"] if args.compute == "f64" else None
-    kernel_file = "syrk_f64.hip"
+    dtype_name = args.compute
     workload = f"sp2_tb_n{n}_{args.storage}storage_{args.compute}"
-    traffic = read_traffic(kernel_file, workload)
-    roofline = {
-        "kernel": "k_syrk_f64",
-        "bound": "mfma",
-        "achieved": round(achieved, 3),
-        "peak": peak,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / peak, 4) if peak else None,
-        "traffic": traffic,
-        "per_launch_flops": flops_per_sq,
-        "avg_launch_ms": round(1e3 * avg_launch_s, 4),
-        "launches_timed": kern_launches,
-    }
+    roofline = dict(lines[dominant])
+    kernel_file = "syrk_f64.hip" if dominant == "f64" else "syrk_lp.hip"
+    roofline["traffic"] = read_traffic(kernel_file, workload)
+    others = [dict(v) for k, v in lines.items() if k != dominant]
 
     cpu = None
     if args.cpu_steps > 0:
@@ -243,15 +265,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "n_occ": n_occ, "gap_eV": args.gap,
                    "storage": args.storage, "compute": args.compute, "tol": args.tol,
-                   "seed": args.seed},
+                   "fp64_prefix": info.fp64_prefix_iters, "seed": args.seed},
         "tflops_algorithmic": round(tflops, 3),
         "iterations": iters,
+        "fp64_prefix_iters": info.fp64_prefix_iters,
+        "refine_steps": info.refine_steps,
         "status": info.status_str,
         "err_rms_vs_fp64_eigh": err_ref,
         "idempotency_fro": idem,
         "trace_error": tr_err,
         "commutator_rms": comm,
         "roofline": roofline,
+        "roofline_other_kernels": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -58,9 +58,11 @@ typedef enum { SP2_F64 = 0, SP2_F32 = 1 } sp2_dtype;
 typedef enum {
     SP2_C_F64 = 0,    /* FP64 MFMA squarings */
     SP2_C_F32 = 1,    /* reserved */
-    SP2_C_F16X2 = 2,  /* reserved */
-    SP2_C_BF16X3 = 3, /* reserved */
-    SP2_C_BF16X2 = 4, /* reserved */
+    SP2_C_F16X2 = 2,  /* mixed: FP64 prefix, then X = h + l (two FP16 planes),
+                         S = hh + hl + lh on FP16 MFMA with FP32 accumulation,
+                         then FP64 refinement */
+    SP2_C_BF16X3 = 3, /* mixed, as above with three BF16 planes (6 products) */
+    SP2_C_BF16X2 = 4, /* mixed, as above with two BF16 planes (3 products) */
     SP2_C_FP8 = 5     /* reserved */
 } sp2_compute;
 
@@ -101,8 +103,9 @@ const char* sp2_status_str(int status);
 /*
  * Bytes of device workspace sp2_density needs for an n x n problem with the
  * given storage type and compute mode (0 for invalid arguments).  The
- * workspace holds two padded FP64 iterates, the per-tile partial sums and the
- * device-side loop state.
+ * workspace holds two padded FP64 iterates (plus two sets of 16-bit planes for
+ * the split modes), the per-tile partial sums, the stream-K fix-up tiles and
+ * the device-side loop state.
  */
 size_t sp2_workspace_size(int n, sp2_dtype dtype, sp2_compute compute);
 
@@ -115,8 +118,20 @@ size_t sp2_workspace_size(int n, sp2_dtype dtype, sp2_compute compute);
  *   n_occ       number of occupied states, 0 <= n_occ <= n.
  *   tol         stop when ||X_m^2 - X_m||_F <= tol (tol > 0).
  *   max_iter    at most this many squarings, 0 <= max_iter <= SP2_MAX_ITER.
- *   compute     arithmetic of the squarings (SP2_C_F64 is built).
- *   fp64_prefix_iters  reserved for the mixed-precision modes (pass -1).
+ *   compute     arithmetic of the squarings.  SP2_C_F64: every step in FP64.
+ *               The split modes (F16X2, BF16X3, BF16X2) run a mixed-precision
+ *               schedule (not in the paper; its dense SP2 is FP64 throughout):
+ *                 1. fp64_prefix_iters trace-steered FP64 steps, while the
+ *                    gap around the Fermi level is still small in the mapped
+ *                    spectrum and rounding errors would be amplified;
+ *                 2. trace-steered steps with split-operand 16-bit products
+ *                    and FP32 accumulation (traces and norms in FP64) until
+ *                    the idempotency stops decreasing;
+ *                 3. FP64 refinement steps alternating X^2 and 2X - X^2
+ *                    (not steered by the trace) until e <= tol, at most 8.
+ *               info->fp64_prefix_iters and info->refine_steps report 1 and 3.
+ *   fp64_prefix_iters  steps of phase 1 for the split modes: -1 = automatic
+ *               (12), otherwise 1..SP2_MAX_ITER; ignored for SP2_C_F64.
  *   workspace   device buffer of at least sp2_workspace_size(n, dtype,
  *               compute) bytes, aligned to SP2_WORKSPACE_ALIGN.
  *   hip_stream  hipStream_t or NULL.
@@ -146,6 +161,8 @@ int sp2_history(const void* workspace, int count, double* tr_hist, double* e_his
  */
 int sp2_profile_enable(int on);
 int sp2_profile_read(double* step_ms_total, int* steps);
+/* The same, split into FP64 step kernels and split-operand step kernels. */
+int sp2_profile_read_split(double* f64_ms, int* f64_steps, double* split_ms, int* split_steps);
 
 #ifdef __cplusplus
 }

@@ -60,6 +60,9 @@ _lib.sp2_profile_enable.restype = ctypes.c_int
 _lib.sp2_profile_enable.argtypes = [ctypes.c_int]
 _lib.sp2_profile_read.restype = ctypes.c_int
 _lib.sp2_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+_lib.sp2_profile_read_split.restype = ctypes.c_int
+_lib.sp2_profile_read_split.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
 
 
 @dataclass
@@ -151,6 +154,8 @@ def sp2_density(H, n_occ: int, tol: float = 1e-10, max_iter: int = 100, compute:
         raise ValueError("D must have H's dtype and leading dimension, row-major")
     if workspace is None:
         workspace = alloc_workspace(n, "f64" if dt == 0 else "f32", compute, device=H.device)
+    elif workspace.numel() < sp2_workspace_size(n, "f64" if dt == 0 else "f32", compute):
+        raise ValueError("workspace too small for this n / compute mode")
     info = sp2_info()
     st = _lib.sp2_density(_vp(H.data_ptr()), _vp(D.data_ptr()), int(n), int(ld), int(n_occ),
                           float(tol), int(max_iter), dt, COMPUTES[compute], int(fp64_prefix_iters),
@@ -189,7 +194,17 @@ def sp2_profile_read():
     return ms.value, steps.value
 
 
+def sp2_profile_read_split():
+    """((FP64 step ms, FP64 steps), (split step ms, split steps)) of the last timed call."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    na, nb = ctypes.c_int(), ctypes.c_int()
+    st = _lib.sp2_profile_read_split(ctypes.byref(a), ctypes.byref(na), ctypes.byref(b), ctypes.byref(nb))
+    if st != OK:
+        raise RuntimeError(f"sp2_profile_read_split failed: {sp2_status_str(st)}")
+    return (a.value, na.value), (b.value, nb.value)
+
+
 def exported_symbols():
     """Names of the C entry points this binding wraps."""
     return ["sp2_version", "sp2_status_str", "sp2_workspace_size", "sp2_density", "sp2_history",
-            "sp2_profile_enable", "sp2_profile_read"]
+            "sp2_profile_enable", "sp2_profile_read", "sp2_profile_read_split"]

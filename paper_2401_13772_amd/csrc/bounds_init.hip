@@ -13,12 +13,12 @@
 // Reductions are deterministic: fixed per-thread order, fixed wave/block
 // order, and a last-arriving block that sums the per-block partials in index
 // order.
-#include "sp2_internal.h"
+#include "sp2_device.h"
 
 namespace sp2 {
 
-__global__ void k_reset(State* st, int n, int n_occ, double tol, int max_iter, unsigned* cnt,
-                        int ncnt) {
+__global__ void k_reset(State* st, int n, int n_occ, double tol, int max_iter, int m0,
+                        unsigned* cnt, int ncnt) {
     for (int i = threadIdx.x; i < ncnt; i += blockDim.x) cnt[i] = 0u;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->emin = 0.0;
@@ -40,6 +40,17 @@ __global__ void k_reset(State* st, int n, int n_occ, double tol, int max_iter, u
     st->fp64_steps = 0;
     st->branch_mask[0] = 0;
     st->branch_mask[1] = 0;
+    st->lp_mask[0] = 0;
+    st->lp_mask[1] = 0;
+    st->phase = 0;
+    st->m0 = m0;
+    st->lp_start = 0;
+    st->lp_steps = 0;
+    st->refine_steps = 0;
+    st->max_refine = 8;
+    st->stale = 0;
+    st->pad0 = 0;
+    st->lp_switch = 0.0;
 }
 
 template <typename T>
@@ -222,30 +233,39 @@ __global__ __launch_bounds__(kThreads) void k_init(const T* __restrict__ H, int 
 }
 
 // D <- last iterate (converted to the storage type), or 0 / I for the special
-// occupations.  Leaves D untouched when the status is negative.
-template <typename T>
+// occupations.  Leaves D untouched when the status is negative.  When the
+// newest iterate lives only in split planes (a solve that ended in the split
+// phase), it is decoded from them.
+template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void k_finalize(T* __restrict__ D, int n, int ld, int ldp,
                                                        const double* __restrict__ x0,
                                                        const double* __restrict__ x1,
-                                                       const State* st) {
+                                                       const uint16_t* __restrict__ p0,
+                                                       const uint16_t* __restrict__ p1,
+                                                       size_t pstride, const State* st) {
     if (st->status < 0) return;
     const int special = st->special;
-    const double* src = (st->iterations & 1) ? x1 : x0;
+    const int odd = st->iterations & 1;
+    const double* src = odd ? x1 : x0;
+    const uint16_t* psrc = odd ? p1 : p0;
+    const bool from_planes = (MODE != SP2_C_F64) && st->stale;
     const int i = blockIdx.x;
     for (int j = threadIdx.x; j < n; j += kThreads) {
         double v;
+        const size_t idx = (size_t)i * ldp + j;
         if (special == 1) v = 0.0;
         else if (special == 2) v = (i == j) ? 1.0 : 0.0;
-        else v = src[(size_t)i * ldp + j];
+        else if (from_planes) v = load_planes<MODE == SP2_C_F64 ? SP2_C_F16X2 : MODE>(psrc, pstride, idx);
+        else v = src[idx];
         D[(size_t)i * ld + j] = (T)v;
     }
 }
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, unsigned* cnt,
-                        int ncnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, st, n, n_occ, tol, max_iter, cnt, ncnt);
+hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, int m0,
+                        unsigned* cnt, int ncnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, st, n, n_occ, tol, max_iter, m0, cnt, ncnt);
     return hipGetLastError();
 }
 
@@ -282,14 +302,34 @@ hipError_t launch_init(const void* H, sp2_dtype dt, int n, int ld, const Layout&
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, const State* st,
-                           const double* x0, const double* x1, hipStream_t s) {
-    if (dt == SP2_F64)
-        hipLaunchKernelGGL(k_finalize<double>, dim3(n), dim3(kThreads), 0, s, (double*)D, n, ld,
-                           L.ldp, x0, x1, st);
-    else
-        hipLaunchKernelGGL(k_finalize<float>, dim3(n), dim3(kThreads), 0, s, (float*)D, n, ld, L.ldp,
-                           x0, x1, st);
+template <typename T>
+static void finalize_t(T* D, int n, int ld, const Layout& L, sp2_compute mode, const State* st,
+                       const double* x0, const double* x1, const uint16_t* p0, const uint16_t* p1,
+                       hipStream_t s) {
+    switch (mode) {
+        case SP2_C_F16X2:
+            hipLaunchKernelGGL((k_finalize<T, SP2_C_F16X2>), dim3(n), dim3(kThreads), 0, s, D, n, ld,
+                               L.ldp, x0, x1, p0, p1, L.plane_stride, st);
+            break;
+        case SP2_C_BF16X3:
+            hipLaunchKernelGGL((k_finalize<T, SP2_C_BF16X3>), dim3(n), dim3(kThreads), 0, s, D, n, ld,
+                               L.ldp, x0, x1, p0, p1, L.plane_stride, st);
+            break;
+        case SP2_C_BF16X2:
+            hipLaunchKernelGGL((k_finalize<T, SP2_C_BF16X2>), dim3(n), dim3(kThreads), 0, s, D, n, ld,
+                               L.ldp, x0, x1, p0, p1, L.plane_stride, st);
+            break;
+        default:
+            hipLaunchKernelGGL((k_finalize<T, SP2_C_F64>), dim3(n), dim3(kThreads), 0, s, D, n, ld,
+                               L.ldp, x0, x1, p0, p1, L.plane_stride, st);
+    }
+}
+
+hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, sp2_compute mode,
+                           const State* st, const double* x0, const double* x1, const uint16_t* p0,
+                           const uint16_t* p1, hipStream_t s) {
+    if (dt == SP2_F64) finalize_t<double>((double*)D, n, ld, L, mode, st, x0, x1, p0, p1, s);
+    else finalize_t<float>((float*)D, n, ld, L, mode, st, x0, x1, p0, p1, s);
     return hipGetLastError();
 }
 

@@ -34,12 +34,13 @@ thread_local HostSlots t_slots[kMaxDevices];
 
 // Optional per-step kernel timing (sp2_profile_enable): an event pair around
 // every SYRK launch on the caller's stream.
+constexpr int kLaunchesPerStep = 2;  // FP64 step kernel, split-operand step kernel
 struct Profile {
     bool on = false;
     bool made = false;
-    hipEvent_t ev[2 * SP2_MAX_ITER];
-    double last_ms = 0.0;
-    int last_steps = 0;
+    hipEvent_t ev[2 * kLaunchesPerStep * SP2_MAX_ITER];
+    double last_ms[2] = {0.0, 0.0};   // [FP64 steps, split-operand steps]
+    int last_steps[2] = {0, 0};
 };
 
 thread_local Profile t_prof[kMaxDevices];
@@ -51,7 +52,7 @@ hipError_t profile_for_current(Profile** out) {
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     Profile& p = t_prof[dev];
     if (p.on && !p.made) {
-        for (int i = 0; i < 2 * SP2_MAX_ITER; ++i) {
+        for (int i = 0; i < 2 * kLaunchesPerStep * SP2_MAX_ITER; ++i) {
             e = hipEventCreate(&p.ev[i]);
             if (e != hipSuccess) return e;
         }
@@ -125,25 +126,39 @@ const char* sp2_status_str(int status) {
     }
 }
 
+static bool compute_built(sp2_compute c) {
+    return c == SP2_C_F64 || c == SP2_C_F16X2 || c == SP2_C_BF16X3 || c == SP2_C_BF16X2;
+}
+
+// FP64 steps before the split phase when the caller passes -1: enough for the
+// spectral gap, mapped into [0, 1], to have opened to O(1) so that later
+// rounding errors are no longer amplified by the remaining steps.
+static int auto_prefix(int n) {
+    (void)n;
+    return 12;
+}
+
 size_t sp2_workspace_size(int n, sp2_dtype dtype, sp2_compute compute) {
     if (n <= 0 || n > 65536) return 0;
     if (dtype != SP2_F64 && dtype != SP2_F32) return 0;
-    if (compute != SP2_C_F64) return 0;
-    return make_layout(n).total;
+    if (!compute_built(compute)) return 0;
+    return make_layout(n, compute).total;
 }
 
 int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, int max_iter,
                 sp2_dtype dtype, sp2_compute compute, int fp64_prefix_iters, void* workspace,
                 size_t workspace_bytes, void* hip_stream, sp2_info* info) {
-    (void)fp64_prefix_iters;
     if (!H || !D || n <= 0 || n > 65536 || ld < n || n_occ < 0 || n_occ > n)
         return fail(info, SP2_E_INVALID);
     if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 0 || max_iter > SP2_MAX_ITER)
         return fail(info, SP2_E_INVALID);
     if (dtype != SP2_F64 && dtype != SP2_F32) return fail(info, SP2_E_INVALID);
     if (compute < SP2_C_F64 || compute > SP2_C_FP8) return fail(info, SP2_E_INVALID);
-    if (compute != SP2_C_F64) return fail(info, SP2_E_UNSUPPORTED);
-    const Layout L = make_layout(n);
+    if (!compute_built(compute)) return fail(info, SP2_E_UNSUPPORTED);
+    if (fp64_prefix_iters < -1 || fp64_prefix_iters > SP2_MAX_ITER) return fail(info, SP2_E_INVALID);
+    const Layout L = make_layout(n, compute);
+    const bool mixed = L.np > 0;
+    const int m0 = mixed ? (fp64_prefix_iters < 0 ? auto_prefix(n) : (fp64_prefix_iters < 1 ? 1 : fp64_prefix_iters)) : 0;
     if (!workspace || workspace_bytes < L.total ||
         (reinterpret_cast<uintptr_t>(workspace) % SP2_WORKSPACE_ALIGN) != 0)
         return fail(info, SP2_E_WORKSPACE);
@@ -160,6 +175,8 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
     double* x1 = (double*)(ws + L.off_x1);
     unsigned* cnt = (unsigned*)(ws + L.off_cnt);
     double* scratch = (double*)(ws + L.off_scratch);
+    uint16_t* p0 = (uint16_t*)(ws + L.off_p0);
+    uint16_t* p1 = (uint16_t*)(ws + L.off_p1);
 
     HostSlots* hs = nullptr;
     SP2_HIP(slots_for_current(&hs));
@@ -167,7 +184,7 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
     SP2_HIP(profile_for_current(&prof));
     const bool timed = prof->on;
 
-    SP2_HIP(launch_reset(st, n, n_occ, tol, max_iter, cnt, L.max_groups + 2, s));
+    SP2_HIP(launch_reset(st, n, n_occ, tol, max_iter, m0, cnt, L.max_groups + 2, s));
     SP2_HIP(launch_bounds(H, dtype, n, ld, L, st, rowpart, part, s));
     SP2_HIP(launch_init(H, dtype, n, ld, L, st, x0, part, s));
 
@@ -177,11 +194,27 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
     while (issued < max_iter && !stop) {
         const int c = (max_iter - issued) < chunk ? (max_iter - issued) : chunk;
         for (int i = 0; i < c; ++i, ++issued) {
-            const double* xc = (issued & 1) ? x1 : x0;
-            double* xn = (issued & 1) ? x0 : x1;
-            if (timed) SP2_HIP(hipEventRecord(prof->ev[2 * issued], s));
-            SP2_HIP(launch_syrk_f64(L, xc, xn, st, part, scratch, cnt, s));
-            if (timed) SP2_HIP(hipEventRecord(prof->ev[2 * issued + 1], s));
+            const int odd = issued & 1;
+            double* xc = odd ? x1 : x0;
+            double* xn = odd ? x0 : x1;
+            uint16_t* pc = odd ? p1 : p0;
+            uint16_t* pn = odd ? p0 : p1;
+            hipEvent_t* ev = timed ? &prof->ev[2 * kLaunchesPerStep * issued] : nullptr;
+            if (mixed && issued >= m0) {
+                // every launch below checks the device state and runs only if the
+                // step is due in its phase, so exactly one of the two step kernels
+                // does the work
+                if (issued == m0) SP2_HIP(launch_f64_to_planes(L, compute, xc, pc, st, issued, s));
+                SP2_HIP(launch_planes_to_f64(L, compute, pc, xc, st, issued, s));
+            }
+            if (timed) SP2_HIP(hipEventRecord(ev[0], s));
+            SP2_HIP(launch_syrk_f64(L, xc, xn, st, part, scratch, cnt, issued, s));
+            if (timed) SP2_HIP(hipEventRecord(ev[1], s));
+            if (mixed && issued >= m0) {
+                if (timed) SP2_HIP(hipEventRecord(ev[2], s));
+                SP2_HIP(launch_syrk_lp(L, compute, pc, pn, st, part, scratch, cnt, issued, s));
+                if (timed) SP2_HIP(hipEventRecord(ev[3], s));
+            }
         }
         SP2_HIP(hipMemcpyAsync(&hs->flags[slot], &st->done, sizeof(int), hipMemcpyDeviceToHost, s));
         SP2_HIP(hipEventRecord(hs->ev[slot], s));
@@ -192,27 +225,29 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
         pending = slot;
         slot ^= 1;
     }
-    SP2_HIP(launch_finalize(D, dtype, n, ld, L, st, x0, x1, s));
+    SP2_HIP(launch_finalize(D, dtype, n, ld, L, compute, st, x0, x1, p0, p1, s));
     SP2_HIP(hipMemcpyAsync(hs->state, st, sizeof(State), hipMemcpyDeviceToHost, s));
     SP2_HIP(hipStreamSynchronize(s));
 
     const State& h = *hs->state;
     if (timed) {
-        double total = 0.0;
+        prof->last_ms[0] = prof->last_ms[1] = 0.0;
+        prof->last_steps[0] = prof->last_steps[1] = 0;
         for (int i = 0; i < h.iterations && i < issued; ++i) {
+            const int lp = (int)((h.lp_mask[i >> 6] >> (i & 63)) & 1ull);
             float ms = 0.f;
-            SP2_HIP(hipEventElapsedTime(&ms, prof->ev[2 * i], prof->ev[2 * i + 1]));
-            total += ms;
+            hipEvent_t* ev = &prof->ev[2 * kLaunchesPerStep * i + 2 * lp];
+            SP2_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            prof->last_ms[lp] += ms;
+            prof->last_steps[lp] += 1;
         }
-        prof->last_ms = total;
-        prof->last_steps = h.iterations < issued ? h.iterations : issued;
     }
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->status = h.status;
         info->iterations = h.iterations;
         info->fp64_prefix_iters = h.fp64_steps;
-        info->refine_steps = 0;
+        info->refine_steps = h.refine_steps;
         info->trace = h.tr;
         info->trace_error = std::fabs(h.tr - (double)n_occ);
         info->idempotency = h.idem;
@@ -234,8 +269,18 @@ int sp2_profile_enable(int on) {
 int sp2_profile_read(double* step_ms_total, int* steps) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SP2_E_HIP;
-    if (step_ms_total) *step_ms_total = t_prof[dev].last_ms;
-    if (steps) *steps = t_prof[dev].last_steps;
+    if (step_ms_total) *step_ms_total = t_prof[dev].last_ms[0] + t_prof[dev].last_ms[1];
+    if (steps) *steps = t_prof[dev].last_steps[0] + t_prof[dev].last_steps[1];
+    return SP2_OK;
+}
+
+int sp2_profile_read_split(double* f64_ms, int* f64_steps, double* split_ms, int* split_steps) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SP2_E_HIP;
+    if (f64_ms) *f64_ms = t_prof[dev].last_ms[0];
+    if (f64_steps) *f64_steps = t_prof[dev].last_steps[0];
+    if (split_ms) *split_ms = t_prof[dev].last_ms[1];
+    if (split_steps) *split_steps = t_prof[dev].last_steps[1];
     return SP2_OK;
 }
 

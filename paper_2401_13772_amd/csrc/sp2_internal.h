@@ -31,30 +31,53 @@ struct State {
     int32_t special;    // 1: n_occ == 0 -> D = 0; 2: n_occ == n -> D = I
     int32_t bad;        // a non-finite entry was seen in H
     uint32_t ticket;    // arrival counter of the last-block reductions
-    int32_t fp64_steps;
+    int32_t fp64_steps; // trace-steered FP64 steps (phase 0)
+    // mixed precision: phase 0 = FP64 prefix, 1 = split-operand steps,
+    // 2 = FP64 refinement (alternating x^2 / 2x - x^2)
+    int32_t phase;
+    int32_t m0;         // FP64 steps before the split phase (0: FP64 only)
+    int32_t lp_start;   // first split-phase step
+    int32_t lp_steps;
+    int32_t refine_steps;
+    int32_t max_refine;
+    int32_t stale;      // 1: the newest iterate lives only in the split planes
+    int32_t pad0;
+    double lp_switch;   // leave the split phase once e <= lp_switch
     uint64_t branch_mask[2];
+    uint64_t lp_mask[2];  // bit m set when step m was a split-operand step
     double tr_hist[SP2_MAX_ITER];
     double e_hist[SP2_MAX_ITER];
 };
 
 // Workspace layout (byte offsets from the 256-byte aligned base).
 struct Layout {
-    int n, ldp, bt;          // padded edge, SYRK tile edge
-    int tiles;               // lower tiles of the SYRK grid
+    int n, ldp, bt;          // padded edge, FP64 SYRK tile edge
+    int tiles;               // lower tiles of the FP64 SYRK grid
     int max_groups;          // stream-K grid bound: min(tiles, kMaxPersistent)
-    size_t off_state, off_part, off_rowpart, off_cnt, off_scratch, off_x0, off_x1, total;
+    int np;                  // 16-bit planes per iterate (0: FP64 only)
+    size_t plane_stride;     // elements between planes of one iterate (ldp^2)
+    size_t off_state, off_part, off_rowpart, off_cnt, off_scratch, off_x0, off_x1;
+    size_t off_p0, off_p1, total;
 };
+
+constexpr int kLpTile = 128;  // tile edge of the split-operand kernels
+
+inline int planes_of(sp2_compute c) {
+    return c == SP2_C_F16X2 ? 2 : c == SP2_C_BF16X3 ? 3 : c == SP2_C_BF16X2 ? 2 : 0;
+}
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // SYRK tile edge for an n x n problem.
 inline int syrk_tile(int n) { return n <= 2048 ? 64 : 128; }
 
-inline Layout make_layout(int n) {
+inline Layout make_layout(int n, sp2_compute compute) {
     Layout L{};
     L.n = n;
     L.bt = syrk_tile(n);
-    L.ldp = (int)align_up((size_t)n, (size_t)L.bt);
+    L.np = planes_of(compute);
+    L.ldp = (int)align_up((size_t)n, (size_t)(L.np ? kLpTile : L.bt));
+    L.plane_stride = (size_t)L.ldp * L.ldp;
     int T = L.ldp / L.bt;
     L.tiles = T * (T + 1) / 2;
     int nb = L.ldp / kBndTile;
@@ -67,10 +90,17 @@ inline Layout make_layout(int n) {
     L.off_state = off;   off = align_up(off + sizeof(State), 256);
     L.off_part = off;    off = align_up(off + part_entries * sizeof(double), 256);
     L.off_rowpart = off; off = align_up(off + ((size_t)nsplit * L.ldp + 2 * (size_t)L.ldp) * sizeof(double), 256);
+    size_t scratch_f64 = 2 * (size_t)(L.max_groups + 1) * L.bt * L.bt * sizeof(double);
+    int Tl = L.ldp / kLpTile;
+    int lp_groups = Tl * (Tl + 1) / 2 < kMaxPersistent ? Tl * (Tl + 1) / 2 : kMaxPersistent;
+    size_t scratch_lp = L.np ? 2 * (size_t)(lp_groups + 1) * kLpTile * kLpTile * sizeof(float) : 0;
+    if (L.np && lp_groups > L.max_groups) L.max_groups = lp_groups;
     L.off_cnt = off;     off = align_up(off + (size_t)(L.max_groups + 2) * sizeof(unsigned), 256);
-    L.off_scratch = off; off = align_up(off + 2 * (size_t)(L.max_groups + 1) * L.bt * L.bt * sizeof(double), 256);
+    L.off_scratch = off; off = align_up(off + (scratch_f64 > scratch_lp ? scratch_f64 : scratch_lp), 256);
     L.off_x0 = off;      off = align_up(off + (size_t)L.ldp * L.ldp * sizeof(double), 256);
     L.off_x1 = off;      off = align_up(off + (size_t)L.ldp * L.ldp * sizeof(double), 256);
+    L.off_p0 = off;      off = align_up(off + (size_t)L.np * L.plane_stride * sizeof(uint16_t), 256);
+    L.off_p1 = off;      off = align_up(off + (size_t)L.np * L.plane_stride * sizeof(uint16_t), 256);
     L.total = off;
     return L;
 }
@@ -126,15 +156,23 @@ __device__ inline bool arrive_last(State* st, unsigned nblocks, int* flag_lds) {
 
 // ---------------------------------------------------------------- host launchers
 
-hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, unsigned* cnt,
-                        int ncnt, hipStream_t s);
+hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, int m0,
+                        unsigned* cnt, int ncnt, hipStream_t s);
 hipError_t launch_bounds(const void* H, sp2_dtype dt, int n, int ld, const Layout& L, State* st,
                          double* rowpart, double* part, hipStream_t s);
 hipError_t launch_init(const void* H, sp2_dtype dt, int n, int ld, const Layout& L, State* st,
                        double* x0, double* part, hipStream_t s);
 hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* st, double* part,
-                           double* scratch, unsigned* cnt, hipStream_t s);
-hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, const State* st,
-                           const double* x0, const double* x1, hipStream_t s);
+                           double* scratch, unsigned* cnt, int step, hipStream_t s);
+hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const uint16_t* Pin, uint16_t* Pout,
+                          State* st, double* part, void* scratch, unsigned* cnt, int step,
+                          hipStream_t s);
+hipError_t launch_planes_to_f64(const Layout& L, sp2_compute mode, const uint16_t* Pin, double* X,
+                                const State* st, int step, hipStream_t s);
+hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, uint16_t* Pout,
+                                const State* st, int step, hipStream_t s);
+hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, sp2_compute mode,
+                           const State* st, const double* x0, const double* x1, const uint16_t* p0,
+                           const uint16_t* p1, hipStream_t s);
 
 }  // namespace sp2

@@ -32,12 +32,9 @@
 //     in that XCD's L2;
 //   * per-tile sums go to a partial buffer that the last-arriving workgroup
 //     adds in tile order: deterministic, no floating-point atomics.
-#include "sp2_internal.h"
+#include "sp2_device.h"
 
 namespace sp2 {
-
-typedef double d2 __attribute__((ext_vector_type(2)));
-typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBK = 16;
 constexpr int kLDK = kBK + 1;
@@ -56,51 +53,6 @@ struct SyrkCfg {
 
 using CfgSmall = SyrkCfg<64, 2, 2>;    // 256 threads, 32 x 32 per wave
 using CfgLarge = SyrkCfg<128, 2, 4>;   // 512 threads, 64 x 32 per wave
-
-// Map the hardware block index to a logical index so that each XCD gets a
-// contiguous range (blocks b, b+8, b+16, ... run on the same XCD).
-__device__ inline unsigned xcd_remap(unsigned b, unsigned nblocks) {
-    const unsigned q = nblocks / 8, r = nblocks % 8;
-    const unsigned x = b % 8, k = b / 8;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
-}
-
-// Logical index -> lower-triangle tile (ti >= tj), row-major over the triangle.
-__device__ inline void tri_tile(unsigned L, int& ti, int& tj) {
-    int i = (int)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
-    while ((unsigned)((i + 1) * (i + 2) / 2) <= L) ++i;
-    while ((unsigned)(i * (i + 1) / 2) > L) --i;
-    ti = i;
-    tj = (int)(L - (unsigned)(i * (i + 1) / 2));
-}
-
-template <int NW>
-__device__ inline double group_sum(double v, double* scratch) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) scratch[w] = v;
-    __syncthreads();
-    double r = scratch[0];
-#pragma unroll
-    for (int i = 1; i < NW; ++i) r += scratch[i];
-    __syncthreads();
-    return r;
-}
-
-template <int NW>
-__device__ inline bool group_arrive_last(unsigned* ticket, unsigned nblocks, int* flag_lds) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(ticket, 1u);
-        *flag_lds = (t == nblocks - 1);
-    }
-    __syncthreads();
-    bool last = *flag_lds != 0;
-    if (last) __threadfence();
-    return last;
-}
 
 // Accumulate the C tile over K slices [kt0, kt1) of the row panels of tiles
 // ti and tj.  DIAG: ti == tj, both operands come from one panel.
@@ -222,60 +174,22 @@ __device__ __forceinline__ void sp2_epilogue(const double* __restrict__ X, doubl
     }
 }
 
-// Device-side steering after the last tile of a step: fixed-order sums of
-// the per-tile partials, the stop tests and the branch for the next step.
-template <class C>
-__device__ __forceinline__ void sp2_steer(State* st, const double* __restrict__ part,
-                                          unsigned ntiles, int grow, double* red) {
-    double E = 0.0, TR = 0.0, F = 0.0;
-    for (unsigned k = threadIdx.x; k < ntiles; k += C::NT) {
-        E += part[4 * k + 0];
-        TR += part[4 * k + 1];
-        F += part[4 * k + 2];
-    }
-    E = group_sum<C::NW>(E, red);
-    TR = group_sum<C::NW>(TR, red);
-    F = group_sum<C::NW>(F, red);
-    if (threadIdx.x == 0) {
-        const int m = st->iterations;
-        const double e = sqrt(E);
-        st->tr_hist[m] = st->tr;
-        st->e_hist[m] = e;
-        if (grow) st->branch_mask[m >> 6] |= 1ull << (m & 63);
-        st->iterations = m + 1;
-        st->fp64_steps = st->fp64_steps + 1;
-        st->tr = TR;
-        st->fro2 = F;
-        st->idem = e;
-        st->grow = (TR - st->nocc <= 0.0) ? 1 : 0;
-        if (e <= st->tol) {
-            st->done = 1;
-            st->status = SP2_OK;
-        } else if (m >= 2 && e >= st->e_hist[m - 2] && e < 0.1) {
-            st->done = 1;
-            st->status = SP2_E_STAGNATED;
-        } else if (m + 1 >= st->max_iter) {
-            st->done = 1;
-            st->status = SP2_E_NOT_CONVERGED;
-        }
-        st->ticket = 0;
-    }
-}
-
 // Stream-K SYRK + SP2 step.  grid = G persistent workgroups (G <= ntiles).
 // scratch: 2 (G + 1) C-tile partials; cnt: G + 1 arrival counters, zero on
-// entry and left zero on exit.
+// entry and left zero on exit.  `step` is the index of the step this launch
+// performs; it does nothing unless the loop state says that step is due and
+// in an FP64 phase (the trace-steered prefix or the refinement).
 template <class C>
 __global__ __launch_bounds__(C::NT) void k_syrk_f64(const double* __restrict__ X,
                                                     double* __restrict__ Y, int ldp, int T,
                                                     State* st, double* __restrict__ part,
                                                     double* __restrict__ scratch,
-                                                    unsigned* __restrict__ cnt) {
+                                                    unsigned* __restrict__ cnt, int step) {
     extern __shared__ double smem[];
     __shared__ double red[C::NW];
     __shared__ int flag;
 
-    if (st->done) return;
+    if (st->done || st->iterations != step || st->phase == 1) return;
     const int grow = st->grow;
     const unsigned G = gridDim.x;
     const unsigned g = xcd_remap(blockIdx.x, G);
@@ -344,13 +258,22 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64(const double* __restrict__ X
             part[4 * t + 2] = fro;
         }
     }
-    if (!group_arrive_last<C::NW>(&st->ticket, G, &flag)) return;
-    sp2_steer<C>(st, part, ntiles, grow, red);
+    if (!group_arrive_last(&st->ticket, G, &flag)) return;
+    double E = 0.0, TR = 0.0, F = 0.0;
+    for (unsigned k = tid; k < ntiles; k += C::NT) {
+        E += part[4 * k + 0];
+        TR += part[4 * k + 1];
+        F += part[4 * k + 2];
+    }
+    E = group_sum<C::NW>(E, red);
+    TR = group_sum<C::NW>(TR, red);
+    F = group_sum<C::NW>(F, red);
+    if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
 }
 
 template <class C>
 static hipError_t launch_cfg(const Layout& L, const double* X, double* Y, State* st, double* part,
-                             double* scratch, unsigned* cnt, hipStream_t s) {
+                             double* scratch, unsigned* cnt, int step, hipStream_t s) {
     static int per_cu = -1;
     static int cus = 0;
     if (per_cu < 0) {
@@ -373,14 +296,14 @@ static hipError_t launch_cfg(const Layout& L, const double* X, double* Y, State*
     if (G > ntiles) G = ntiles;
     if (G < 1) G = 1;
     hipLaunchKernelGGL(k_syrk_f64<C>, dim3(G), dim3(C::NT), C::LDS, s, X, Y, L.ldp, T, st, part,
-                       scratch, cnt);
+                       scratch, cnt, step);
     return hipGetLastError();
 }
 
 hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* st, double* part,
-                           double* scratch, unsigned* cnt, hipStream_t s) {
-    if (L.bt == CfgSmall::BT) return launch_cfg<CfgSmall>(L, X, Y, st, part, scratch, cnt, s);
-    return launch_cfg<CfgLarge>(L, X, Y, st, part, scratch, cnt, s);
+                           double* scratch, unsigned* cnt, int step, hipStream_t s) {
+    if (L.bt == CfgSmall::BT) return launch_cfg<CfgSmall>(L, X, Y, st, part, scratch, cnt, step, s);
+    return launch_cfg<CfgLarge>(L, X, Y, st, part, scratch, cnt, step, s);
 }
 
 }  // namespace sp2

@@ -1,0 +1,440 @@
+// syrk_lp.hip -- one SP2 step with split-operand 16-bit products on the gfx950
+// matrix cores (the low-precision phase of a mixed-precision solve).
+//
+// The iterate X (|x| <= 1) is held as 16-bit planes (see sp2_device.h):
+// FP16 x2 (h + l), BF16 x3 or BF16 x2.  S = X X^T is formed from the plane
+// products hi*hi + hi*lo + lo*hi (+ the next order for BF16 x3) with
+// v_mfma_f32_16x16x32_{f16,bf16}, accumulated in FP32.  The epilogue is the
+// same SP2 update as the FP64 step (Section "SP2 solver": X' = X^2 or
+// 2X - X^2 by the trace), evaluated in FP64 from the decoded X and the FP32
+// product; it writes the planes of X' (they are the iterate during this
+// phase: no FP64 copy is stored) and the per-tile e^2, trace and ||X'||^2.
+// Steering is taken by the last-arriving workgroup (sp2_steer_thread0).
+//
+// Design for CDNA4:
+//   * 128 x 128 tiles of the lower block triangle, 4 wave64s each owning
+//     64 x 64 (16 accumulator blocks, one FP32 accumulator per block);
+//   * operand panels go straight from global memory to LDS with the 16-byte
+//     LDS-DMA load (global_load_lds_dwordx4): no staging registers.  Each
+//     wave instruction fills 1 KiB = 16 rows x 64 B; a row's four 16-byte
+//     chunks are stored XOR-swizzled by (row >> 1) & 3 so that the eight lanes
+//     a ds_read_b128 serves per cycle hit distinct banks;
+//   * double-buffered K slices of 32 elements, one barrier per slice;
+//   * the same stream-K schedule, XCD renumbering and order-independent
+//     split-tile fix-up as the FP64 step.
+#include "sp2_device.h"
+
+namespace sp2 {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLBK = 32;  // K slice in 16-bit elements (64 bytes per row)
+
+template <int BT_, int WM_, int WN_, int MODE_>
+struct LpCfg {
+    static constexpr int BT = BT_, WM = WM_, WN = WN_, MODE = MODE_;
+    static constexpr int NT = 64 * WM * WN, NW = WM * WN;
+    static constexpr int WTM = BT / WM, WTN = BT / WN;
+    static constexpr int MI = WTM / 16, NI = WTN / 16;
+    static constexpr int NP = Planes<MODE>::NP;
+    static constexpr int PANEL_BYTES = BT * kLBK * 2;          // one plane of one panel
+    static constexpr int STAGE_BYTES = NP * 2 * PANEL_BYTES;
+    static constexpr int CLD = BT + 1;                          // padded row of the LDS C tile (floats)
+    static constexpr size_t CTILE = (size_t)BT * CLD * sizeof(float);
+    static constexpr size_t LDS = 2 * (size_t)STAGE_BYTES > CTILE ? 2 * (size_t)STAGE_BYTES : CTILE;
+    static constexpr int BLOCKS = PANEL_BYTES / 1024;           // 1 KiB LDS-DMA blocks per panel plane
+    static constexpr int BPW = BLOCKS / NW;                     // ... per wave
+    static_assert(BLOCKS % NW == 0, "panel must split evenly over the waves");
+};
+
+template <int MODE>
+__device__ __forceinline__ f4 mfma16(const uint4& a, const uint4& b, f4 c) {
+    if constexpr (MODE == SP2_C_F16X2)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int swz(int row) { return (row >> 1) & 3; }
+
+// Issue the LDS-DMA loads of one K slice (all planes, both panels) into `stage`.
+template <class C, bool DIAG>
+__device__ __forceinline__ void lp_issue(const uint16_t* __restrict__ P, size_t pstride, int ldp,
+                                         int rowA, int rowB, int k0, char* stage) {
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+    for (int p = 0; p < C::NP; ++p) {
+#pragma unroll
+        for (int q = 0; q < (DIAG ? 1 : 2); ++q) {
+            const int prow0 = q ? rowB : rowA;
+#pragma unroll
+            for (int j = 0; j < C::BPW; ++j) {
+                const int blk = w * C::BPW + j;
+                const int row = blk * 16 + (lane >> 2);
+                const int c = (lane & 3) ^ swz(row);
+                const uint16_t* src = P + p * pstride + (size_t)(prow0 + row) * ldp + k0 + 8 * c;
+                char* dst = stage + (p * 2 + q) * C::PANEL_BYTES + blk * 1024;
+                __builtin_amdgcn_global_load_lds((const void*)src,
+                                                 (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+            }
+        }
+    }
+}
+
+template <class C, bool DIAG>
+__device__ __forceinline__ void lp_mainloop(const uint16_t* __restrict__ P, size_t pstride, int ldp,
+                                            int ti, int tj, int kt0, int kt1, char* smem,
+                                            f4 (&acc)[C::MI][C::NI]) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w / C::WN, wn = w % C::WN;
+    const int rowA = ti * C::BT, rowB = tj * C::BT;
+    lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, kt0 * kLBK, smem);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    // fragment addressing: row r of the wave's sub-tile, chunk c = lane >> 4
+    int aoff[C::MI], boff[C::NI];
+#pragma unroll
+    for (int mi = 0; mi < C::MI; ++mi) {
+        const int row = wm * C::WTM + mi * 16 + (lane & 15);
+        aoff[mi] = row * 64 + (((lane >> 4) ^ swz(row)) << 4);
+    }
+#pragma unroll
+    for (int ni = 0; ni < C::NI; ++ni) {
+        const int row = wn * C::WTN + ni * 16 + (lane & 15);
+        boff[ni] = row * 64 + (((lane >> 4) ^ swz(row)) << 4);
+    }
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int stg = (kt - kt0) & 1;
+        if (kt + 1 < kt1)
+            lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, (kt + 1) * kLBK, smem + (stg ^ 1) * C::STAGE_BYTES);
+        const char* S = smem + stg * C::STAGE_BYTES;
+        uint4 af[C::NP][C::MI], bf[C::NP][C::NI];
+#pragma unroll
+        for (int p = 0; p < C::NP; ++p) {
+            const char* pa = S + (p * 2 + 0) * C::PANEL_BYTES;
+            const char* pb = DIAG ? pa : S + (p * 2 + 1) * C::PANEL_BYTES;
+#pragma unroll
+            for (int mi = 0; mi < C::MI; ++mi) af[p][mi] = *(const uint4*)(pa + aoff[mi]);
+#pragma unroll
+            for (int ni = 0; ni < C::NI; ++ni) bf[p][ni] = *(const uint4*)(pb + boff[ni]);
+        }
+        // products ordered small to large; each pass touches all blocks before
+        // the next pass reuses an accumulator
+        if constexpr (C::NP == 3) {
+#pragma unroll
+            for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[2][mi], bf[0][ni], acc[mi][ni]);
+#pragma unroll
+            for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[1][mi], bf[1][ni], acc[mi][ni]);
+#pragma unroll
+            for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[2][ni], acc[mi][ni]);
+        }
+#pragma unroll
+        for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[1][mi], bf[0][ni], acc[mi][ni]);
+#pragma unroll
+        for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[1][ni], acc[mi][ni]);
+#pragma unroll
+        for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[0][ni], acc[mi][ni]);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    }
+}
+
+// Accumulators -> padded LDS tile C[BT][BT+1] (floats).  Accumulator layout of
+// v_mfma_f32_16x16x32_{f16,bf16} (checked on gfx950): lane l holds column l%16
+// of the 16x16 block at rows 4*(l/16) + r, r = 0..3.
+template <class C>
+__device__ __forceinline__ void lp_acc_to_lds(const f4 (&acc)[C::MI][C::NI], float* Cs) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w / C::WN, wn = w % C::WN;
+#pragma unroll
+    for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < C::NI; ++ni) {
+            const int r0 = wm * C::WTM + mi * 16 + 4 * (lane >> 4);
+            const int c = wn * C::WTN + ni * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Cs[(r0 + r) * C::CLD + c] = acc[mi][ni][r];
+        }
+}
+
+// SP2 update of one finished tile held in LDS (Cs = S tile).  Each thread
+// handles runs of 8 consecutive elements of a row, so every global plane
+// access is one 16-byte vector.
+//   pass A: the tile itself (rows of ti, columns of tj): X' from S and the
+//           decoded X, the tile's e^2 / trace / ||X'||^2, the new planes;
+//   pass B (off-diagonal tiles): the mirrored tile (rows of tj), from the
+//           transposed LDS tile and X read at the mirrored place (the planes
+//           are bitwise symmetric, so X' comes out bit-identical).
+// Diagonal tiles take the lower triangle's S for both halves.
+template <class C>
+__device__ __forceinline__ void lp_epilogue(const uint16_t* __restrict__ Pin, uint16_t* __restrict__ Pout,
+                                            size_t pstride, int ldp, int ti, int tj, int grow,
+                                            const float* Cs, double& e2, double& trp, double& fro) {
+    constexpr int RUN = 8;
+    constexpr int RUNS_PER_ROW = C::BT / RUN;
+    const bool diag = (ti == tj);
+    typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+    for (int pass = 0; pass < (diag ? 1 : 2); ++pass) {
+        const int rbase = (pass == 0 ? ti : tj) * C::BT;
+        const int cbase = (pass == 0 ? tj : ti) * C::BT;
+        for (int q = threadIdx.x; q < C::BT * RUNS_PER_ROW; q += C::NT) {
+            const int r = q / RUNS_PER_ROW, c0 = (q % RUNS_PER_ROW) * RUN;
+            const size_t g = (size_t)(rbase + r) * ldp + cbase + c0;
+            u16x8 xin[C::NP], xout[C::NP];
+#pragma unroll
+            for (int p = 0; p < C::NP; ++p) xin[p] = *(const u16x8*)(Pin + p * pstride + g);
+#pragma unroll
+            for (int k = 0; k < RUN; ++k) {
+                const int c = c0 + k;
+                // S at (row r, col c) of this pass's tile
+                float sf;
+                if (pass == 1) sf = Cs[c * C::CLD + r];                        // mirrored tile
+                else if (diag && c > r) sf = Cs[c * C::CLD + r];               // upper half of a diagonal tile
+                else sf = Cs[r * C::CLD + c];
+                uint16_t v[C::NP];
+#pragma unroll
+                for (int p = 0; p < C::NP; ++p) v[p] = xin[p][k];
+                const double x = Planes<C::MODE>::decode(v);
+                const double sd = (double)sf;
+                const double xn = grow ? (2.0 * x - sd) : sd;
+                if (pass == 0) {
+                    const double d = sd - x;
+                    const double wgt = diag ? 1.0 : 2.0;
+                    e2 += wgt * (d * d);
+                    fro += wgt * (xn * xn);
+                    if (diag && c == r) trp += xn;
+                }
+                uint16_t o[C::NP];
+                Planes<C::MODE>::encode(xn, o);
+#pragma unroll
+                for (int p = 0; p < C::NP; ++p) xout[p][k] = o[p];
+            }
+#pragma unroll
+            for (int p = 0; p < C::NP; ++p) *(u16x8*)(Pout + p * pstride + g) = xout[p];
+        }
+    }
+}
+
+// Stream-K split-operand step (phase 1 only).  `step` is the index of the
+// step this launch performs; it does nothing unless the loop state says that
+// step is due and in the split-precision phase.
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_syrk_lp(const uint16_t* __restrict__ Pin,
+                                                   uint16_t* __restrict__ Pout, size_t pstride,
+                                                   int ldp, int T, State* st, double* __restrict__ part,
+                                                   float* __restrict__ scratch,
+                                                   unsigned* __restrict__ cnt, int step) {
+    extern __shared__ __attribute__((aligned(16))) char lsmem[];
+    __shared__ double red[C::NW];
+    __shared__ int flag;
+
+    if (st->done || st->iterations != step || st->phase != 1) return;
+    const int grow = st->grow;
+    const unsigned G = gridDim.x;
+    const unsigned g = xcd_remap(blockIdx.x, G);
+    const int KT = ldp / kLBK;
+    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
+    const uint64_t U = (uint64_t)ntiles * KT;
+    const uint64_t u0 = U * g / G, u1 = U * (g + 1) / G;
+    const int tid = threadIdx.x;
+
+    uint64_t u = u0;
+    while (u < u1) {
+        const unsigned t = (unsigned)(u / KT);
+        const int k0 = (int)(u % KT);
+        const uint64_t kend = (uint64_t)k0 + (u1 - u);
+        const int k1 = kend < (uint64_t)KT ? (int)kend : KT;
+        int ti, tj;
+        tri_tile(t, ti, tj);
+        f4 acc[C::MI][C::NI];
+#pragma unroll
+        for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+        if (ti == tj) lp_mainloop<C, true>(Pin, pstride, ldp, ti, tj, k0, k1, lsmem, acc);
+        else lp_mainloop<C, false>(Pin, pstride, ldp, ti, tj, k0, k1, lsmem, acc);
+        u += (uint64_t)(k1 - k0);
+
+        float* Cs = (float*)lsmem;       // the stage buffers are free after the main loop
+        lp_acc_to_lds<C>(acc, Cs);
+        __syncthreads();
+        if (!(k0 == 0 && k1 == KT)) {
+            // split tile: seg 0 = [0, kb) ends at this group's range end
+            // (boundary g + 1); seg 1 = [kb, KT) starts at its range start.
+            const int seg = (k0 == 0) ? 0 : 1;
+            const unsigned bidx = (seg == 0) ? g + 1 : g;
+            const size_t tile_elems = (size_t)C::BT * C::BT;
+            float* mine = scratch + (2 * (size_t)bidx + seg) * tile_elems;
+            const float* other = scratch + (2 * (size_t)bidx + (1 - seg)) * tile_elems;
+            for (int i = tid; i < C::BT * C::BT; i += C::NT)
+                mine[i] = Cs[(i / C::BT) * C::CLD + (i % C::BT)];
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) flag = (int)atomicAdd(&cnt[bidx], 1u);
+            __syncthreads();
+            if (flag == 0) continue;             // the other segment will finish the tile
+            __threadfence();
+            for (int i = tid; i < C::BT * C::BT; i += C::NT) {
+                float* c = &Cs[(i / C::BT) * C::CLD + (i % C::BT)];
+                const float o = other[i];
+                *c = (seg == 0) ? (*c + o) : (o + *c);
+            }
+            if (tid == 0) cnt[bidx] = 0u;
+            __syncthreads();
+        }
+
+        double e2 = 0.0, trp = 0.0, fro = 0.0;
+        lp_epilogue<C>(Pin, Pout, pstride, ldp, ti, tj, grow, Cs, e2, trp, fro);
+        e2 = group_sum<C::NW>(e2, red);
+        trp = group_sum<C::NW>(trp, red);
+        fro = group_sum<C::NW>(fro, red);
+        if (tid == 0) {
+            part[4 * t + 0] = e2;
+            part[4 * t + 1] = trp;
+            part[4 * t + 2] = fro;
+        }
+    }
+    if (!group_arrive_last(&st->ticket, G, &flag)) return;
+    double E = 0.0, TR = 0.0, F = 0.0;
+    for (unsigned k = tid; k < ntiles; k += C::NT) {
+        E += part[4 * k + 0];
+        TR += part[4 * k + 1];
+        F += part[4 * k + 2];
+    }
+    E = group_sum<C::NW>(E, red);
+    TR = group_sum<C::NW>(TR, red);
+    F = group_sum<C::NW>(F, red);
+    if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
+}
+
+// The FP64 iterate from its planes, once, when the split-precision phase
+// hands over to the FP64 refinement (step `step`).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_planes_to_f64(const uint16_t* __restrict__ Pin,
+                                                            size_t pstride, double* __restrict__ X,
+                                                            size_t count, const State* st, int step) {
+    if (st->done || st->iterations != step || st->phase != 2 || !st->stale) return;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * kThreads)
+        X[i] = load_planes<MODE>(Pin, pstride, i);
+}
+
+// The planes of the FP64 iterate, once, when the FP64 prefix hands over to the
+// split-precision phase (at the start of step `step` = m0).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_f64_to_planes(const double* __restrict__ X,
+                                                            uint16_t* __restrict__ Pout, size_t pstride,
+                                                            size_t count, const State* st, int step) {
+    if (st->done || st->iterations != step || st->phase != 1 || st->lp_steps != 0) return;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * kThreads)
+        store_planes<MODE>(Pout, pstride, i, X[i]);
+}
+
+template <class C>
+static hipError_t launch_lp_cfg(const Layout& L, const uint16_t* Pin, uint16_t* Pout, State* st,
+                                double* part, float* scratch, unsigned* cnt, int step, hipStream_t s) {
+    static int per_cu = -1;
+    static int cus = 0;
+    if (per_cu < 0) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_syrk_lp<C>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+        if (e != hipSuccess) return e;
+        int dev = 0, nb = 0;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_syrk_lp<C>, C::NT, C::LDS);
+        if (e != hipSuccess) return e;
+        per_cu = nb < 1 ? 1 : nb;
+    }
+    const int T = L.ldp / C::BT;
+    const int ntiles = T * (T + 1) / 2;
+    int G = per_cu * cus;
+    if (G > kMaxPersistent) G = kMaxPersistent;
+    if (G > ntiles) G = ntiles;
+    if (G < 1) G = 1;
+    hipLaunchKernelGGL(k_syrk_lp<C>, dim3(G), dim3(C::NT), C::LDS, s, Pin, Pout, L.plane_stride, L.ldp,
+                       T, st, part, scratch, cnt, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const uint16_t* Pin, uint16_t* Pout,
+                          State* st, double* part, void* scratch, unsigned* cnt, int step,
+                          hipStream_t s) {
+    float* sc = (float*)scratch;
+    switch (mode) {
+        case SP2_C_F16X2:
+            return launch_lp_cfg<LpCfg<128, 2, 2, SP2_C_F16X2>>(L, Pin, Pout, st, part, sc, cnt, step, s);
+        case SP2_C_BF16X3:
+            return launch_lp_cfg<LpCfg<128, 2, 2, SP2_C_BF16X3>>(L, Pin, Pout, st, part, sc, cnt, step, s);
+        case SP2_C_BF16X2:
+            return launch_lp_cfg<LpCfg<128, 2, 2, SP2_C_BF16X2>>(L, Pin, Pout, st, part, sc, cnt, step, s);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_planes_to_f64(const Layout& L, sp2_compute mode, const uint16_t* Pin, double* X,
+                                const State* st, int step, hipStream_t s) {
+    const size_t count = (size_t)L.ldp * L.ldp;
+    const int blocks = 2048;
+    switch (mode) {
+        case SP2_C_F16X2:
+            hipLaunchKernelGGL(k_planes_to_f64<SP2_C_F16X2>, dim3(blocks), dim3(kThreads), 0, s, Pin,
+                               L.plane_stride, X, count, st, step);
+            break;
+        case SP2_C_BF16X3:
+            hipLaunchKernelGGL(k_planes_to_f64<SP2_C_BF16X3>, dim3(blocks), dim3(kThreads), 0, s, Pin,
+                               L.plane_stride, X, count, st, step);
+            break;
+        case SP2_C_BF16X2:
+            hipLaunchKernelGGL(k_planes_to_f64<SP2_C_BF16X2>, dim3(blocks), dim3(kThreads), 0, s, Pin,
+                               L.plane_stride, X, count, st, step);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, uint16_t* Pout,
+                                const State* st, int step, hipStream_t s) {
+    const size_t count = (size_t)L.ldp * L.ldp;
+    const int blocks = 2048;
+    switch (mode) {
+        case SP2_C_F16X2:
+            hipLaunchKernelGGL(k_f64_to_planes<SP2_C_F16X2>, dim3(blocks), dim3(kThreads), 0, s, X, Pout,
+                               L.plane_stride, count, st, step);
+            break;
+        case SP2_C_BF16X3:
+            hipLaunchKernelGGL(k_f64_to_planes<SP2_C_BF16X3>, dim3(blocks), dim3(kThreads), 0, s, X, Pout,
+                               L.plane_stride, count, st, step);
+            break;
+        case SP2_C_BF16X2:
+            hipLaunchKernelGGL(k_f64_to_planes<SP2_C_BF16X2>, dim3(blocks), dim3(kThreads), 0, s, X, Pout,
+                               L.plane_stride, count, st, step);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sp2
