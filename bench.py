@@ -7,13 +7,19 @@ through the C ABI: Gershgorin bounds, X_0, every trace-steered squaring until
 the timed region starts.
 
 Default workload: n = 4096 (1024 atoms x 4 orbitals), n_occ = 2048, HOMO-LUMO
-gap opened to 0.5 eV, H stored in FP32, tol 1e-10.
+gap opened to 0.5 eV, H stored in FP32, tol 1e-10, mixed precision (FP64
+prefix, split-operand FP16 x2 squarings on the 16-bit matrix cores, FP64
+refinement).  The same run also times the plain FP64 solve, which is both the
+accuracy reference of the metric ("vs FP64 SP2") and the speed-up baseline.
 
 Printed (one JSON line on stdout): density matrices per second, algorithmic
-TFLOP/s (n^2 (n+1) per symmetric squaring), accuracy against an FP64
-eigendecomposition of the same stored H, the roofline position of the
-squaring kernel from HIP events taken around each of its launches inside the
-timed region, and the FP64 CPU oracle timed on a bounded sample on this host.
+TFLOP/s (n^2 (n+1) per symmetric squaring), accuracy against the FP64 GPU
+solve and against an FP64 eigendecomposition of the same stored H, the
+roofline position of the dominant squaring kernel from HIP events taken
+around each of its launches inside the timed region, the roofline fraction of
+the whole mixed solve (sum over squarings of executed flops / peak of their
+precision, over the wall time), and the FP64 CPU oracle timed on a bounded
+sample on this host.
 """
 from __future__ import annotations
 
@@ -67,25 +73,45 @@ def read_traffic(kernel_file, workload):
         return None
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(H64, n_occ, iterations, steps):
-    """The FP64 oracle's SP2 loop on this host, `steps` squarings of the same
-    workload, scaled to density matrices per second with the GPU's iteration
-    count."""
+    """The FP64 oracle's SP2 loop on this host: `steps` squarings of the same
+    workload (a bounded sample), scaled to density matrices per second with
+    the FP64 solve's iteration count.  Also times the oracle's Jacobi
+    eigendecomposition route to D on a 256-orbital matrix of the same model
+    (one thread), for scale."""
     import oracle
+    from tbgen import make_tb_hamiltonian
     threads = len(os.sched_getaffinity(0))
     threads = min(threads, oracle.max_threads()) if oracle.max_threads() > 0 else threads
     t0 = time.perf_counter()
     r = oracle.sp2(H64, n_occ, tol=1e-10, max_iter=steps, nthreads=threads)
     dt = time.perf_counter() - t0
     per_step = dt / max(r.iterations, 1)
+    small = make_tb_hamiltonian(256, seed=0, gap=0.5)
+    t1 = time.perf_counter()
+    oracle.jacobi_dm(small.H, small.n_occ)
+    dj = time.perf_counter() - t1
     return {
         "value": 1.0 / (per_step * iterations),
         "unit": "DM/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"oracle_sp2 (plain C triple loops, FP64, OpenMP over rows) ran the first "
-                   f"{r.iterations} of {iterations} squarings of the same n={H64.shape[0]} solve "
-                   f"in {dt:.2f} s; value = 1/({per_step:.3f} s x {iterations})"),
+        "cpu_model": cpu_model(),
+        "sample": (f"oracle_sp2 (plain C triple loops, FP64, OpenMP over rows, {threads} threads) ran "
+                   f"the first {r.iterations} of the {iterations} squarings of the same n={H64.shape[0]} "
+                   f"FP64 solve in {dt:.2f} s; value = 1/({per_step:.3f} s x {iterations})"),
+        "jacobi_dm_n256_1thread_s": round(dj, 3),
     }
 
 
@@ -101,76 +127,29 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--gap", type=float, default=0.5)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--compute", default="f64", choices=["f64", "f16x2", "bf16x3", "bf16x2"])
-    ap.add_argument("--prefix", type=int, default=-1,
-                    help="FP64 steps before the split-operand phase (-1 = library default)")
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--cpu-steps", type=int, default=1,
-                    help="oracle squarings in the CPU-baseline sample (0 = skip)")
-    ap.add_argument("--no-reference", action="store_true",
-                    help="skip the FP64 eigendecomposition accuracy check (profiling runs)")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
-                    help="only run a plain copy of BYTES bytes (counter scaling) and exit")
-    args = ap.parse_args()
+PRODUCTS = {"f64": 1, "f16x2": 3, "bf16x3": 6, "bf16x2": 3}
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
+def timed_solves(sp2, H, D, ws, n_occ, args, compute, steps, warmup, stream):
+    """warmup + `steps` timed solves; per-kernel HIP-event sums of the squarings."""
     import torch
 
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-
-    import paper_2401_13772_amd as sp2
-    from tbgen import make_tb_hamiltonian
-
-    n = args.n
-    n_occ = n // 2
-    storage = np.float32 if args.storage == "f32" else np.float64
-    log(f"generating tight-binding H n={n} seed={args.seed} gap={args.gap} storage={args.storage}")
-    t0 = time.perf_counter()
-    inst = make_tb_hamiltonian(n, args.seed, gap=args.gap, dtype=storage)
-    log(f"  generated in {time.perf_counter() - t0:.1f} s")
-    dev = torch.device("cuda:0")
-    H = torch.from_numpy(inst.H).to(dev)
-    D = torch.empty_like(H)
-    ws = sp2.alloc_workspace(n, args.storage, args.compute, device=dev)
-    stream = torch.cuda.current_stream()
-
     def solve():
-        _, info = sp2.sp2_density(H, n_occ, tol=args.tol, max_iter=sp2.MAX_ITER,
-                                  compute=args.compute, fp64_prefix_iters=args.prefix, D=D,
-                                  workspace=ws, stream=stream)
+        _, info = sp2.sp2_density(H, n_occ, tol=args.tol, max_iter=sp2.MAX_ITER, compute=compute,
+                                  fp64_prefix_iters=args.prefix, D=D, workspace=ws, stream=stream)
         if info.status < 0:
             raise RuntimeError(f"sp2_density: {info.status_str}")
         return info
 
-    log(f"warmup x{args.warmup}")
-    for _ in range(args.warmup):
-        info = solve()
+    for _ in range(warmup):
+        solve()
     torch.cuda.synchronize()
-
-    log(f"timed x{args.steps}")
     sp2.sp2_profile_enable(True)
     kern = {"f64": [0.0, 0], "split": [0.0, 0]}
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         infos.append(solve())
         (fm, fk), (lm, lk) = sp2.sp2_profile_read_split()
         kern["f64"][0] += fm
@@ -180,18 +159,13 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     sp2.sp2_profile_enable(False)
-    info = infos[-1]
-    iters = info.iterations
-    ms_per_step = 1e3 * elapsed / args.steps
-    dms = args.steps / elapsed
+    return elapsed, infos, kern
+
+
+def kernel_lines(kern, n, elapsed, compute):
     flops_per_sq = float(n) * n * (n + 1)
-    flops_per_dm = sum(i.iterations for i in infos) / len(infos) * flops_per_sq
-    tflops = flops_per_dm * dms / 1e12
-    products = {"f64": 1, "f16x2": 3, "bf16x3": 6, "bf16x2": 3}[args.compute]
-    kinds = {
-        "f64": ("k_syrk_f64", PEAKS_TFLOPS["f64"], 1),
-        "split": ("k_syrk_lp", PEAKS_TFLOPS["bf16"], products),
-    }
+    kinds = {"f64": ("k_syrk_f64", PEAKS_TFLOPS["f64"], 1),
+             "split": ("k_syrk_lp", PEAKS_TFLOPS["f16"], PRODUCTS[compute])}
     lines = {}
     for key, (ms_tot, launches) in kern.items():
         if launches == 0:
@@ -213,9 +187,182 @@ def main():
             "launches_timed": launches,
             "share_of_solve": round(ms_tot / (1e3 * elapsed), 4),
         }
+    return lines
+
+
+def bench_batch(args):
+    """512 problems with sizes uniform on {64, 68, ..., 512} (n_occ = n/2, gap
+    0.5 eV, FP32 storage, FP64 squarings): one graph replay of the batched plan
+    vs the same problems as 512 separate sp2_density calls.  A step is one
+    solve of the whole batch; value = density matrices per second."""
+    import numpy as np
+    import torch
+
+    import paper_2401_13772_amd as sp2
+    from tbgen import batch_sizes, make_tb_hamiltonian
+    sizes = [int(v) for v in batch_sizes(args.batch, seed=args.seed)]
+    log(f"generating {len(sizes)} tight-binding Hamiltonians (n 64..512)")
+    t0 = time.perf_counter()
+    Hs, nocc = [], []
+    for k, n in enumerate(sizes):
+        inst = make_tb_hamiltonian(n, seed=10_000 + k, gap=args.gap, dtype=np.float32)
+        Hs.append(torch.from_numpy(inst.H).cuda())
+        nocc.append(inst.n_occ)
+    log(f"  generated in {time.perf_counter() - t0:.1f} s")
+    cache = args.autotune_cache or None
+    plan = sp2.Plan(sizes, nocc, dtype="f32", tol=args.tol, max_iter=args.batch_max_iter,
+                    autotune_cache=cache)
+    Ds = [torch.empty_like(H) for H in Hs]
+    for _ in range(args.warmup):
+        plan.run(Hs, Ds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, infos = plan.run(Hs, Ds)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    assert all(i.status == 0 for i in infos), "a batched solve did not converge"
+    # baseline: 512 plain launches of the single-matrix solve
+    ws = sp2.alloc_workspace(max(sizes), "f32", "f64")
+    D1 = [torch.empty_like(H) for H in Hs]
+    for k in range(len(sizes)):
+        sp2.sp2_density(Hs[k], nocc[k], tol=args.tol, D=D1[k], workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    iters = 0
+    for k in range(len(sizes)):
+        _, i1 = sp2.sp2_density(Hs[k], nocc[k], tol=args.tol, D=D1[k], workspace=ws)
+        iters += i1.iterations
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t1
+    same = all(torch.equal(a, b) for a, b in zip(Ds, D1)) if cache is None else None
+    flops = sum(float(n) * n * (n + 1) * i.iterations for n, i in zip(sizes, infos))
+    per_batch = el / args.steps
+    out = {
+        "metric": METRIC, "value": round(len(sizes) / per_batch, 2), "unit": "DM/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * per_batch, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"sp2_tb_batch{len(sizes)}_n64to512_f32storage_f64", "batch": len(sizes),
+                   "gap_eV": args.gap, "tol": args.tol, "tile_shape": plan.config},
+        "tflops_algorithmic": round(flops / per_batch / 1e12, 3),
+        "roofline": {"bound": "mfma", "achieved": round(flops / per_batch / 1e12, 3),
+                     "peak": PEAKS_TFLOPS["f64"], "unit": "TFLOP/s",
+                     "frac": round(flops / per_batch / 1e12 / PEAKS_TFLOPS["f64"], 4),
+                     "note": "whole batched solve (all kernels) against the FP64 matrix peak"},
+        "plain_launches": {"value": round(len(sizes) / el1, 2), "unit": "DM/s", "ms": round(1e3 * el1, 3),
+                           "iterations_total": iters},
+        "speedup_vs_plain_launches": round(el1 / per_batch, 3),
+        "bitwise_equal_to_plain": same,
+        "max_idempotency": max(i.idempotency for i in infos),
+        "max_trace_error": max(i.trace_error for i in infos),
+    }
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--gap", type=float, default=0.5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--compute", default="f16x2", choices=["f64", "f16x2", "bf16x3", "bf16x2"])
+    ap.add_argument("--prefix", type=int, default=-1,
+                    help="FP64 steps before the split-operand phase (-1 = library default)")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--fp64-steps", type=int, default=5,
+                    help="timed plain-FP64 solves (accuracy reference and speed-up baseline; 0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=6,
+                    help="oracle squarings in the CPU-baseline sample (0 = skip)")
+    ap.add_argument("--no-reference", action="store_true",
+                    help="skip the FP64 eigendecomposition accuracy check (profiling runs)")
+    ap.add_argument("--workload", default="single", choices=["single", "batch"],
+                    help="single: one n x n solve (default); batch: the batched plan (512 problems)")
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--batch-max-iter", type=int, default=60)
+    ap.add_argument("--autotune-cache", default="",
+                    help="batch: autotune the tile shape with this cache file (default: no autotune)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy of BYTES bytes (counter scaling) and exit")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+
+    if args.workload == "batch":
+        bench_batch(args)
+        return
+
+    import paper_2401_13772_amd as sp2
+    from tbgen import make_tb_hamiltonian
+
+    n = args.n
+    n_occ = n // 2
+    storage = np.float32 if args.storage == "f32" else np.float64
+    log(f"generating tight-binding H n={n} seed={args.seed} gap={args.gap} storage={args.storage}")
+    t0 = time.perf_counter()
+    inst = make_tb_hamiltonian(n, args.seed, gap=args.gap, dtype=storage)
+    log(f"  generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    H = torch.from_numpy(inst.H).to(dev)
+    stream = torch.cuda.current_stream()
+    flops_per_sq = float(n) * n * (n + 1)
+
+    # plain FP64 SP2: the metric's accuracy reference and the speed-up baseline
+    fp64 = None
+    D64 = None
+    if args.compute != "f64" and args.fp64_steps > 0:
+        log(f"FP64 leg: warmup x1, timed x{args.fp64_steps}")
+        D64 = torch.empty_like(H)
+        ws64 = sp2.alloc_workspace(n, args.storage, "f64", device=dev)
+        el64, inf64, kern64 = timed_solves(sp2, H, D64, ws64, n_occ, args, "f64", args.fp64_steps, 1, stream)
+        l64 = kernel_lines(kern64, n, el64, "f64")["f64"]
+        fp64 = {"value": round(args.fp64_steps / el64, 4), "unit": "DM/s",
+                "ms_per_step": round(1e3 * el64 / args.fp64_steps, 4), "iterations": inf64[-1].iterations,
+                "status": inf64[-1].status_str, "k_syrk_f64": l64}
+        del ws64
+        torch.cuda.empty_cache()
+        log(f"  FP64: {fp64['ms_per_step']:.3f} ms/DM, {inf64[-1].iterations} squarings, "
+            f"k_syrk_f64 {l64['avg_launch_ms']:.4f} ms = {l64['achieved']:.1f} TFLOP/s")
+
+    D = torch.empty_like(H)
+    ws = sp2.alloc_workspace(n, args.storage, args.compute, device=dev)
+    log(f"main leg ({args.compute}): warmup x{args.warmup}, timed x{args.steps}")
+    elapsed, infos, kern = timed_solves(sp2, H, D, ws, n_occ, args, args.compute, args.steps,
+                                        args.warmup, stream)
+    info = infos[-1]
+    iters = info.iterations
+    ms_per_step = 1e3 * elapsed / args.steps
+    dms = args.steps / elapsed
+    flops_per_dm = sum(i.iterations for i in infos) / len(infos) * flops_per_sq
+    tflops = flops_per_dm * dms / 1e12
+    lines = kernel_lines(kern, n, elapsed, args.compute)
     dominant = max(lines, key=lambda k: kern[k][0])
+    # roofline fraction of the whole solve: sum over squarings of executed
+    # flops / peak of their precision, over the wall time
+    peak_time = 0.0
+    for key, (ms_tot, launches) in kern.items():
+        if launches:
+            peak = PEAKS_TFLOPS["f64"] if key == "f64" else PEAKS_TFLOPS["f16"]
+            mult = 1 if key == "f64" else PRODUCTS[args.compute]
+            peak_time += launches * flops_per_sq * mult / (peak * 1e12)
+    solve_frac = peak_time / elapsed
     log(f"status={info.status_str} iterations={iters} (FP64 prefix {info.fp64_prefix_iters}, "
-        f"refine {info.refine_steps}) {ms_per_step:.3f} ms/DM {dms:.2f} DM/s {tflops:.2f} TFLOP/s")
+        f"refine {info.refine_steps}) {ms_per_step:.3f} ms/DM {dms:.2f} DM/s {tflops:.2f} TFLOP/s "
+        f"solve roofline fraction {solve_frac:.3f}")
     for key, ln in lines.items():
         log(f"  {ln['kernel']}: {ln['launches_timed']} launches, {ln['avg_launch_ms']:.4f} ms avg, "
             f"{ln['achieved']:.1f} TFLOP/s algorithmic ({ln['executed_tflops']:.1f} executed), "
@@ -227,6 +374,10 @@ def main():
     idem = float(torch.linalg.norm(Dg @ Dg - Dg))
     comm = float(torch.linalg.norm(Hd @ Dg - Dg @ Hd)) / np.sqrt(n)
     tr_err = abs(float(torch.trace(Dg)) - n_occ)
+    err_fp64 = None
+    if D64 is not None:
+        err_fp64 = float(torch.linalg.norm(Dg - D64.double())) / np.sqrt(n)
+        log(f"  rms|D - D_fp64_sp2| = {err_fp64:.3e}")
     err_ref = None
     if not args.no_reference:
         log("FP64 eigendecomposition of the stored H (accuracy reference)")
@@ -237,17 +388,18 @@ def main():
         log(f"  eigh {time.perf_counter() - t0:.1f} s; rms|D - D_ref| = {err_ref:.3e}")
         del Dref
 
-    dtype_name = args.compute
     workload = f"sp2_tb_n{n}_{args.storage}storage_{args.compute}"
     roofline = dict(lines[dominant])
     kernel_file = "syrk_f64.hip" if dominant == "f64" else "syrk_lp.hip"
-    roofline["traffic"] = read_traffic(kernel_file, workload)
+    tw = workload if dominant != "f64" else f"sp2_tb_n{n}_{args.storage}storage_f64"
+    roofline["traffic"] = read_traffic(kernel_file, tw)
     others = [dict(v) for k, v in lines.items() if k != dominant]
 
     cpu = None
     if args.cpu_steps > 0:
         log(f"CPU oracle sample: {args.cpu_steps} squarings")
-        cpu = cpu_baseline(inst.H.astype(np.float64), n_occ, iters, args.cpu_steps)
+        it64 = fp64["iterations"] if fp64 else iters
+        cpu = cpu_baseline(inst.H.astype(np.float64), n_occ, it64, args.cpu_steps)
         log(f"  {cpu['sample']}")
 
     out = {
@@ -261,7 +413,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype_name,
+        "dtype": args.compute,
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "n_occ": n_occ, "gap_eV": args.gap,
                    "storage": args.storage, "compute": args.compute, "tol": args.tol,
@@ -271,10 +423,16 @@ def main():
         "fp64_prefix_iters": info.fp64_prefix_iters,
         "refine_steps": info.refine_steps,
         "status": info.status_str,
+        "err_rms_vs_fp64_sp2": err_fp64,
         "err_rms_vs_fp64_eigh": err_ref,
+        "meets_1e-6": None if err_fp64 is None and err_ref is None else
+        bool(max(e for e in (err_fp64, err_ref) if e is not None) <= 1e-6),
         "idempotency_fro": idem,
         "trace_error": tr_err,
         "commutator_rms": comm,
+        "fp64_sp2": fp64,
+        "speedup_vs_fp64_sp2": None if fp64 is None else round(dms / fp64["value"], 3),
+        "solve_roofline_frac": round(solve_frac, 4),
         "roofline": roofline,
         "roofline_other_kernels": others,
         "cpu_baseline": cpu,

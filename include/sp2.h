@@ -143,6 +143,89 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
                 size_t workspace_bytes, void* hip_stream, sp2_info* info);
 
 /*
+ * Batched plan (many independent solves in one graph replay).  The paper's
+ * graph-partitioned workflow (Section "Graph-based Divide electronic
+ * structure") solves one small dense SP2 problem per part, independently;
+ * a plan runs a fixed set of such problems together.
+ *
+ * sp2_plan_create: batch problems of sizes n[b] (1 <= n[b] <= SP2_PLAN_MAX_N)
+ *   and occupations n_occ[b], storage dtype, compute (SP2_C_F64; other modes
+ *   return SP2_E_UNSUPPORTED), stop tolerance and max_iter as in sp2_density.
+ *   Allocates the plan's device memory (iterates, loop states, work lists),
+ *   picks the squaring kernel's tile shape and captures the whole solve
+ *   (bounds, X_0, max_iter steps, copy to D, info) into one HIP graph on the
+ *   current device.  autotune_cache: NULL = the single-matrix kernels' tile
+ *   shape (each D is then bitwise equal to its sp2_density result); a file
+ *   path = time the candidate shapes on this size mix once and keep the
+ *   fastest, reading/appending the choice in that text file.  Returns
+ *   SP2_OK and *plan, or a negative status with *plan = NULL.
+ * sp2_plan_run: H[b], D[b] are device pointers to n[b] x n[b] row-major
+ *   matrices (leading dimension n[b]) in the caller's order; D[b] must not
+ *   overlap H[b].  Copies the pointers to the device, replays the graph on
+ *   hip_stream and returns after the per-matrix infos (host array of batch
+ *   records, may be NULL) are back.  Returns the most negative per-matrix
+ *   status if any is negative, else the largest.  Runs of one plan must not
+ *   overlap; the plan is bound to the device it was created on.
+ * sp2_plan_config: name of the chosen tile shape (static storage).
+ * sp2_plan_destroy: frees everything the plan owns.
+ */
+typedef struct sp2_plan sp2_plan;
+#define SP2_PLAN_MAX_BATCH 65536
+#define SP2_PLAN_MAX_N 2048
+int sp2_plan_create(sp2_plan** plan, int batch, const int* n, const int* n_occ, sp2_dtype dtype,
+                    sp2_compute compute, double tol, int max_iter, const char* autotune_cache);
+int sp2_plan_run(sp2_plan* plan, const void* const* H, void* const* D, void* hip_stream,
+                 sp2_info* infos);
+const char* sp2_plan_config(const sp2_plan* plan);
+int sp2_plan_destroy(sp2_plan* plan);
+
+/*
+ * Learned recursive expansion: a composition of trained quadratic maps of the
+ * matrix, a deep-network form of the paper's recursive polynomial expansion
+ * (Section "GPU friendly algorithms": the expansion is a product of layers,
+ * each a low-order polynomial of the previous layer's output).  Layer k with
+ * f_k(x) = a_k x^2 + b_k x + c_k maps X -> f_k(X) when tr X > n_occ and
+ * X -> I - f_k(I - X) otherwise (trace steering as in SP2; (a, b, c) =
+ * (1, 0, 0) is SP2).  Coefficients are FP32 values (held as double).
+ *
+ * sp2_learned_create: a model from n_layers x 3 host coefficients.
+ * sp2_learned_fit: train n_layers layers on spectra, starting from SP2:
+ *   spectra = the eigenvalues of n_samples Hamiltonians, each sorted
+ *   ascending, concatenated (n[s] values each, n[s] <= 1024); gersh = emin,
+ *   emax per sample (the Gershgorin bounds the solve will use); the target is
+ *   the projector (1 on the n_occ[s] lowest levels).  Loss: mean over samples
+ *   of log(mean squared eigenvalue error); Adam over `epochs` passes in
+ *   minibatches of 512, order drawn from `seed`.  Runs on the current GPU
+ *   (allocates its own buffers).  n_layers * max n[s] * 8 <= 150 KiB.
+ * sp2_learned_coefficients: copies up to `capacity` coefficients (3 per
+ *   layer) and the last epoch's loss; returns the layer count.
+ * sp2_learned_save / sp2_learned_load: text file (hex floats, exact).
+ * sp2_learned_density: batch matrices of one size n (device pointers,
+ *   row-major, leading dimension n, storage dtype), occupations n_occ[b]:
+ *   the trained layers, then one SP2 step whose input must satisfy
+ *   ||X^2 - X||_F <= idem_fallback and |tr - n_occ| <= idem_fallback; D gets
+ *   the output of that step.  Matrices that fail are solved again from H by
+ *   plain FP64 SP2 (tol 1e-10) and reported as SP2_E_FALLBACK, with
+ *   info.refine_steps = the learned steps taken before the rejection.
+ *   compute: SP2_C_F64 (others SP2_E_UNSUPPORTED).  The model keeps an
+ *   inference plan for the last (batch, n, n_occ, dtype, bar) and a
+ *   workspace for the fallback solves; calls on one model must not overlap.
+ *   Returns the most negative per-matrix status if any, else the largest.
+ * sp2_learned_destroy: frees the model and what it keeps.
+ */
+typedef struct sp2_learned sp2_learned;
+int sp2_learned_create(sp2_learned** model, int n_layers, const double* coef);
+int sp2_learned_fit(sp2_learned** model, int n_layers, const double* spectra, const int* n,
+                    const int* n_occ, int n_samples, const double* gersh, int epochs, uint64_t seed);
+int sp2_learned_coefficients(const sp2_learned* model, double* coef, int capacity, double* fit_loss);
+int sp2_learned_save(const sp2_learned* model, const char* path);
+int sp2_learned_load(sp2_learned** model, const char* path);
+int sp2_learned_density(sp2_learned* model, int batch, int n, const void* const* H, void* const* D,
+                        const int* n_occ, sp2_dtype dtype, sp2_compute compute, double idem_fallback,
+                        void* hip_stream, sp2_info* infos);
+int sp2_learned_destroy(sp2_learned* model);
+
+/*
  * Copy the per-step history of the last sp2_density call that used
  * `workspace`: tr_hist[m] = tr X_m (before step m), e_hist[m] = e_m.
  * Copies min(count, iterations) entries into the host arrays (either may be

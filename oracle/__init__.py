@@ -64,6 +64,11 @@ def _load():
         lib.oracle_sp2_step_entries.argtypes = [d, ctypes.c_int, ctypes.c_int, i, i,
                                                 ctypes.c_int, d]
         lib.oracle_sp2_step_entries.restype = None
+        u64 = ctypes.POINTER(ctypes.c_uint64)
+        lib.oracle_learned_spectral.argtypes = [d, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                ctypes.c_double, d, ctypes.c_int, d, u64, d]
+        lib.oracle_learned_matrix.argtypes = [d, ctypes.c_int, ctypes.c_int, d, ctypes.c_int,
+                                              ctypes.c_int, d, u64]
         _lib = lib
     return _lib
 
@@ -190,3 +195,39 @@ def sp2_step_entries(X, grow, I, J):
     _load().oracle_sp2_step_entries(_dp(X), X.shape[0], int(grow), _ip(I), _ip(J), I.size,
                                     _dp(out))
     return out
+
+
+def _coef(coef):
+    c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64).reshape(-1, 3))
+    return c, c.shape[0]
+
+
+def learned_spectral(eigvals, n_occ, emin, emax, coef):
+    """The learned recursive expansion on eigenvalues (layer maps a x^2 + b x + c,
+    particle-hole form when tr <= n_occ).  coef: (layers, 3).
+    Returns (x_final, branches, traces)."""
+    lam = np.ascontiguousarray(np.asarray(eigvals, dtype=np.float64))
+    c, L = _coef(coef)
+    x = np.empty(lam.size)
+    mask = (ctypes.c_uint64 * 2)()
+    trh = np.zeros(max(L, 1))
+    st = _load().oracle_learned_spectral(_dp(lam), lam.size, int(n_occ), float(emin), float(emax),
+                                         _dp(c), L, _dp(x), mask, _dp(trh))
+    if st != OK:
+        raise ValueError(f"oracle_learned_spectral status {st}")
+    m = int(mask[0]) | (int(mask[1]) << 64)
+    return x, [(m >> k) & 1 for k in range(L)], trh[:L]
+
+
+def learned_matrix(H, n_occ, coef, nthreads=1):
+    """The learned recursive expansion on the matrix H.  Returns (D, branches)."""
+    H = _f64(H)
+    c, L = _coef(coef)
+    D = np.empty_like(H)
+    mask = (ctypes.c_uint64 * 2)()
+    st = _load().oracle_learned_matrix(_dp(H), H.shape[0], int(n_occ), _dp(c), L, int(nthreads),
+                                       _dp(D), mask)
+    if st != OK:
+        raise ValueError(f"oracle_learned_matrix status {st}")
+    m = int(mask[0]) | (int(mask[1]) << 64)
+    return D, [(m >> k) & 1 for k in range(L)]

@@ -28,6 +28,18 @@
  *                        (a polynomial of H acts on each eigenvalue alone).
  *   oracle_sp2_step_entries  single entries of one SP2 step, for sampled
  *                        checks at sizes where the full loop is too slow.
+ *   oracle_learned_spectral, oracle_learned_matrix
+ *                        a learned recursive expansion: a composition of
+ *                        trained quadratic maps of the matrix (Section "GPU
+ *                        friendly algorithms" describes the recursive
+ *                        polynomial expansion as a product of layers, each a
+ *                        low-order polynomial of the previous layer's output,
+ *                        like a deep network).  Layer k maps
+ *                        X -> f_k(X) = a_k X^2 + b_k X + c_k I when
+ *                        tr X > n_occ and X -> I - f_k(I - X) otherwise (the
+ *                        particle-hole form of the same map; with
+ *                        (a, b, c) = (1, 0, 0) the two branches are SP2's X^2
+ *                        and 2X - X^2).  On eigenvalues and on the matrix.
  *
  * Readings where the paper is silent (also listed in the design notes):
  *   - H is used through its symmetric part Hs = (H + H^T)/2.
@@ -412,4 +424,97 @@ void oracle_sp2_step_entries(const double* X, int n, int grow, const int* I, con
         for (int k = 0; k < n; ++k) s += X[(long)i * n + k] * X[(long)k * n + j];
         out[t] = grow ? 2.0 * X[(long)i * n + j] - s : s;
     }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Learned recursive expansion                                             */
+/* ---------------------------------------------------------------------- */
+
+/* One layer on a scalar: f(x) = a x^2 + b x + c, or 1 - f(1 - x). */
+static double learned_map(double x, const double* abc, int particle_hole)
+{
+    double a = abc[0], b = abc[1], c = abc[2];
+    if (!particle_hole) return a * (x * x) + b * x + c;
+    double y = 1.0 - x;
+    return 1.0 - (a * (y * y) + b * y + c);
+}
+
+/*
+ * The learned expansion on eigenvalues: x_i = (emax - lambda_i)/(emax - emin),
+ * then n_layers layers (coef: 3 per layer), each taking the particle-hole
+ * form when tr - n_occ <= 0 (the trace is taken before the layer, as in SP2).
+ * x_out (n) receives the final x_i; branch_mask (2 words, may be NULL) the
+ * branch of every layer; tr_hist (n_layers, may be NULL) the traces.
+ */
+int oracle_learned_spectral(const double* lambda, int n, int n_occ, double emin, double emax,
+                            const double* coef, int n_layers, double* x_out, uint64_t* branch_mask,
+                            double* tr_hist)
+{
+    if (n <= 0 || !lambda || !x_out || !coef || n_occ < 0 || n_occ > n || n_layers < 0 ||
+        n_layers > 128)
+        return ORACLE_INVALID;
+    if (!(emax > emin)) return ORACLE_DEGENERATE;
+    if (branch_mask) branch_mask[0] = branch_mask[1] = 0;
+    for (int i = 0; i < n; ++i) x_out[i] = (emax - lambda[i]) / (emax - emin);
+    for (int k = 0; k < n_layers; ++k) {
+        double tr = 0.0;
+        for (int i = 0; i < n; ++i) tr += x_out[i];
+        int ph = (tr - (double)n_occ <= 0.0);
+        if (tr_hist) tr_hist[k] = tr;
+        if (ph && branch_mask) branch_mask[k / 64] |= (uint64_t)1 << (k % 64);
+        for (int i = 0; i < n; ++i) x_out[i] = learned_map(x_out[i], coef + 3 * k, ph);
+    }
+    return ORACLE_OK;
+}
+
+/*
+ * The learned expansion on the matrix H (n x n): Gershgorin bounds, X_0 as in
+ * SP2, then each layer literally as written above (S = X X or (I-X)(I-X) by
+ * the triple loop, then the combination).  D receives X after the last layer.
+ */
+int oracle_learned_matrix(const double* H, int n, int n_occ, const double* coef, int n_layers,
+                          int nthreads, double* D, uint64_t* branch_mask)
+{
+    if (n <= 0 || !H || !D || !coef || n_occ < 0 || n_occ > n || n_layers < 0 || n_layers > 128)
+        return ORACLE_INVALID;
+    double emin, emax;
+    int st = oracle_gershgorin(H, n, &emin, &emax);
+    if (st != ORACLE_OK) return st;
+    if (!(emax > emin)) return ORACLE_DEGENERATE;
+    long nn = (long)n * n;
+    double* X = (double*)malloc(sizeof(double) * (size_t)nn);
+    double* Y = (double*)malloc(sizeof(double) * (size_t)nn);
+    double* S = (double*)malloc(sizeof(double) * (size_t)nn);
+    if (!X || !Y || !S) { free(X); free(Y); free(S); return ORACLE_NOMEM; }
+    if (branch_mask) branch_mask[0] = branch_mask[1] = 0;
+    oracle_sp2_init(H, n, emin, emax, X);
+    for (int k = 0; k < n_layers; ++k) {
+        const double a = coef[3 * k], b = coef[3 * k + 1], c = coef[3 * k + 2];
+        double tr = trace_of(X, n);
+        int ph = (tr - (double)n_occ <= 0.0);
+        if (ph && branch_mask) branch_mask[k / 64] |= (uint64_t)1 << (k % 64);
+        if (!ph) {
+            square(X, S, n, nthreads);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    long q = (long)i * n + j;
+                    X[q] = a * S[q] + b * X[q] + (i == j ? c : 0.0);
+                }
+        } else {
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    long q = (long)i * n + j;
+                    Y[q] = (i == j ? 1.0 : 0.0) - X[q];
+                }
+            square(Y, S, n, nthreads);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    long q = (long)i * n + j;
+                    X[q] = (i == j ? 1.0 : 0.0) - (a * S[q] + b * Y[q] + (i == j ? c : 0.0));
+                }
+        }
+    }
+    memcpy(D, X, sizeof(double) * (size_t)nn);
+    free(X); free(Y); free(S);
+    return ORACLE_OK;
 }

@@ -53,6 +53,36 @@ _lib.sp2_density.restype = ctypes.c_int
 _lib.sp2_density.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                              ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
                              ctypes.c_size_t, _vp, ctypes.POINTER(sp2_info)]
+_lib.sp2_plan_create.restype = ctypes.c_int
+_lib.sp2_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_int, ctypes.c_char_p]
+_lib.sp2_plan_run.restype = ctypes.c_int
+_lib.sp2_plan_run.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(sp2_info)]
+_lib.sp2_plan_config.restype = ctypes.c_char_p
+_lib.sp2_plan_config.argtypes = [_vp]
+_lib.sp2_plan_destroy.restype = ctypes.c_int
+_lib.sp2_plan_destroy.argtypes = [_vp]
+PLAN_MAX_N = 2048
+_lib.sp2_learned_create.restype = ctypes.c_int
+_lib.sp2_learned_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+_lib.sp2_learned_fit.restype = ctypes.c_int
+_lib.sp2_learned_fit.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_uint64]
+_lib.sp2_learned_coefficients.restype = ctypes.c_int
+_lib.sp2_learned_coefficients.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_double)]
+_lib.sp2_learned_save.restype = ctypes.c_int
+_lib.sp2_learned_save.argtypes = [_vp, ctypes.c_char_p]
+_lib.sp2_learned_load.restype = ctypes.c_int
+_lib.sp2_learned_load.argtypes = [ctypes.POINTER(_vp), ctypes.c_char_p]
+_lib.sp2_learned_density.restype = ctypes.c_int
+_lib.sp2_learned_density.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, _vp, ctypes.POINTER(sp2_info)]
+_lib.sp2_learned_destroy.restype = ctypes.c_int
+_lib.sp2_learned_destroy.argtypes = [_vp]
 _lib.sp2_history.restype = ctypes.c_int
 _lib.sp2_history.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double), _vp]
@@ -178,6 +208,163 @@ def sp2_history(workspace, count: int = MAX_ITER, stream=None):
     return np.array(tr[:m]), np.array(e[:m])
 
 
+class Plan:
+    """A batched plan (sp2_plan_create): `sizes[b]` x `sizes[b]` problems with
+    occupations n_occ[b], solved together by run() in one graph replay."""
+
+    def __init__(self, sizes, n_occ, dtype: str = "f64", compute: str = "f64", tol: float = 1e-10,
+                 max_iter: int = 100, autotune_cache: str = None):
+        self.sizes = [int(v) for v in sizes]
+        self.n_occ = [int(v) for v in n_occ]
+        if len(self.sizes) != len(self.n_occ) or not self.sizes:
+            raise ValueError("sizes and n_occ must be non-empty and of equal length")
+        self.dtype = dtype
+        self.batch = len(self.sizes)
+        self._h = _vp()
+        ns = (ctypes.c_int * self.batch)(*self.sizes)
+        no = (ctypes.c_int * self.batch)(*self.n_occ)
+        st = _lib.sp2_plan_create(ctypes.byref(self._h), self.batch, ns, no, DTYPES[dtype],
+                                  COMPUTES[compute], float(tol), int(max_iter),
+                                  autotune_cache.encode() if autotune_cache else None)
+        if st != OK:
+            self._h = _vp()
+            raise RuntimeError(f"sp2_plan_create failed: {sp2_status_str(st)} ({st})")
+        self.last_status = None
+
+    @property
+    def config(self) -> str:
+        return _lib.sp2_plan_config(self._h).decode()
+
+    def run(self, Hs, Ds=None, stream=None):
+        """Solve every problem: Hs[b] contiguous (n_b, n_b) device tensors of the
+        plan's dtype.  Returns (Ds, [Info]); pass Ds to reuse buffers."""
+        import torch
+        if not self._h:
+            raise RuntimeError("plan is closed")
+        want = torch.float64 if self.dtype == "f64" else torch.float32
+        if len(Hs) != self.batch:
+            raise ValueError("one H per problem of the plan")
+        for H, n in zip(Hs, self.sizes):
+            if H.dtype != want or tuple(H.shape) != (n, n) or not H.is_contiguous():
+                raise ValueError("H[b] must be a contiguous (n_b, n_b) tensor of the plan's dtype")
+        if Ds is None:
+            Ds = [torch.empty_like(H) for H in Hs]
+        for D, H in zip(Ds, Hs):
+            if D.dtype != want or D.shape != H.shape or not D.is_contiguous():
+                raise ValueError("D[b] must match H[b]")
+        hp = (_vp * self.batch)(*[H.data_ptr() for H in Hs])
+        dp = (_vp * self.batch)(*[D.data_ptr() for D in Ds])
+        infos = (sp2_info * self.batch)()
+        st = _lib.sp2_plan_run(self._h, hp, dp, _stream_handle(stream), infos)
+        self.last_status = int(st)
+        if st == E_HIP or st == E_INVALID and not any(int(i.status) == E_INVALID for i in infos):
+            raise RuntimeError(f"sp2_plan_run failed: {sp2_status_str(st)} ({st})")
+        return Ds, [_info(i) for i in infos]
+
+    def close(self):
+        if self._h:
+            _lib.sp2_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Learned:
+    """A learned recursive expansion (sp2_learned_*): trained quadratic layers
+    with trace steering, SP2 check step and plain-SP2 fallback."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def from_coefficients(cls, coef):
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64).reshape(-1, 3))
+        h = _vp()
+        st = _lib.sp2_learned_create(ctypes.byref(h), c.shape[0],
+                                     c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if st != OK:
+            raise RuntimeError(f"sp2_learned_create failed: {sp2_status_str(st)}")
+        return cls(h)
+
+    @classmethod
+    def fit(cls, n_layers, spectra, n_occ, gersh, epochs, seed=0):
+        """spectra: list of ascending eigenvalue arrays; gersh: (samples, 2)."""
+        import numpy as np
+        lam = np.ascontiguousarray(np.concatenate([np.asarray(w, dtype=np.float64) for w in spectra]))
+        ns = np.ascontiguousarray([len(w) for w in spectra], dtype=np.int32)
+        no = np.ascontiguousarray(n_occ, dtype=np.int32)
+        g = np.ascontiguousarray(np.asarray(gersh, dtype=np.float64).reshape(-1, 2))
+        h = _vp()
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        st = _lib.sp2_learned_fit(ctypes.byref(h), int(n_layers), lam.ctypes.data_as(dp), ns.ctypes.data_as(ip),
+                                  no.ctypes.data_as(ip), len(spectra), g.ctypes.data_as(dp), int(epochs),
+                                  int(seed))
+        if st != OK:
+            raise RuntimeError(f"sp2_learned_fit failed: {sp2_status_str(st)}")
+        return cls(h)
+
+    @classmethod
+    def load(cls, path):
+        h = _vp()
+        st = _lib.sp2_learned_load(ctypes.byref(h), str(path).encode())
+        if st != OK:
+            raise RuntimeError(f"sp2_learned_load failed: {sp2_status_str(st)}")
+        return cls(h)
+
+    def save(self, path):
+        st = _lib.sp2_learned_save(self._h, str(path).encode())
+        if st != OK:
+            raise RuntimeError(f"sp2_learned_save failed: {sp2_status_str(st)}")
+
+    def coefficients(self):
+        """((layers, 3) array, loss of the last training epoch)."""
+        import numpy as np
+        L = _lib.sp2_learned_coefficients(self._h, None, 0, None)
+        c = np.zeros(3 * max(L, 1))
+        loss = ctypes.c_double()
+        _lib.sp2_learned_coefficients(self._h, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 3 * L,
+                                      ctypes.byref(loss))
+        return c[:3 * L].reshape(L, 3), loss.value
+
+    def density(self, Hs, n_occ, Ds=None, idem_fallback=1e-6, compute="f64", stream=None):
+        """Batch of same-size (n, n) contiguous device matrices.  Returns (Ds, [Info])."""
+        import torch
+        n = Hs[0].shape[0]
+        dt = _dtype_code(Hs[0].dtype)
+        for H in Hs:
+            if tuple(H.shape) != (n, n) or H.dtype != Hs[0].dtype or not H.is_contiguous():
+                raise ValueError("all H must be contiguous (n, n) tensors of one dtype")
+        if Ds is None:
+            Ds = [torch.empty_like(H) for H in Hs]
+        b = len(Hs)
+        hp = (_vp * b)(*[H.data_ptr() for H in Hs])
+        dp = (_vp * b)(*[D.data_ptr() for D in Ds])
+        no = (ctypes.c_int * b)(*[int(v) for v in n_occ])
+        infos = (sp2_info * b)()
+        st = _lib.sp2_learned_density(self._h, b, n, hp, dp, no, dt, COMPUTES[compute], float(idem_fallback),
+                                      _stream_handle(stream), infos)
+        if st == E_HIP or st == E_UNSUPPORTED:
+            raise RuntimeError(f"sp2_learned_density failed: {sp2_status_str(st)}")
+        return Ds, [_info(i) for i in infos]
+
+    def close(self):
+        if self._h:
+            _lib.sp2_learned_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def sp2_profile_enable(on: bool = True) -> None:
     st = _lib.sp2_profile_enable(1 if on else 0)
     if st != OK:
@@ -206,5 +393,8 @@ def sp2_profile_read_split():
 
 def exported_symbols():
     """Names of the C entry points this binding wraps."""
-    return ["sp2_version", "sp2_status_str", "sp2_workspace_size", "sp2_density", "sp2_history",
+    return ["sp2_version", "sp2_status_str", "sp2_workspace_size", "sp2_density", "sp2_history", "sp2_plan_create", "sp2_plan_run",
+            "sp2_plan_config", "sp2_plan_destroy", "sp2_learned_create", "sp2_learned_fit",
+            "sp2_learned_coefficients", "sp2_learned_save", "sp2_learned_load", "sp2_learned_density",
+            "sp2_learned_destroy",
             "sp2_profile_enable", "sp2_profile_read", "sp2_profile_read_split"]

@@ -21,36 +21,7 @@ __global__ void k_reset(State* st, int n, int n_occ, double tol, int max_iter, i
                         unsigned* cnt, int ncnt) {
     for (int i = threadIdx.x; i < ncnt; i += blockDim.x) cnt[i] = 0u;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    st->emin = 0.0;
-    st->emax = 0.0;
-    st->tr = 0.0;
-    st->fro2 = 0.0;
-    st->idem = 0.0;
-    st->tol = tol;
-    st->nocc = (double)n_occ;
-    st->n = n;
-    st->max_iter = max_iter;
-    st->grow = 0;
-    st->done = 0;
-    st->status = SP2_E_NOT_CONVERGED;
-    st->iterations = 0;
-    st->special = 0;
-    st->bad = 0;
-    st->ticket = 0;
-    st->fp64_steps = 0;
-    st->branch_mask[0] = 0;
-    st->branch_mask[1] = 0;
-    st->lp_mask[0] = 0;
-    st->lp_mask[1] = 0;
-    st->phase = 0;
-    st->m0 = m0;
-    st->lp_start = 0;
-    st->lp_steps = 0;
-    st->refine_steps = 0;
-    st->max_refine = 8;
-    st->stale = 0;
-    st->pad0 = 0;
-    st->lp_switch = 0.0;
+    state_reset(st, n, n_occ, tol, max_iter, m0);
 }
 
 template <typename T>
@@ -203,33 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_init(const T* __restrict__ H, int 
     }
     t = block_sum(t, red);
     f = block_sum(f, red);
-    if (tid == 0) {
-        st->tr = t;
-        st->fro2 = f;
-        st->grow = (t - st->nocc <= 0.0) ? 1 : 0;
-        const int nn = st->n;
-        if (st->bad) {
-            st->status = SP2_E_INVALID;
-            st->done = 1;
-        } else if (st->nocc == 0.0) {
-            st->special = 1;
-            st->status = SP2_OK;
-            st->done = 1;
-            st->tr = 0.0;
-        } else if (st->nocc == (double)nn) {
-            st->special = 2;
-            st->status = SP2_OK;
-            st->done = 1;
-            st->tr = (double)nn;
-        } else if (!(emax > emin)) {
-            st->status = SP2_E_DEGENERATE;
-            st->done = 1;
-        } else if (st->max_iter == 0) {
-            st->status = SP2_E_NOT_CONVERGED;
-            st->done = 1;
-        }
-        st->ticket = 0;
-    }
+    if (tid == 0) state_after_init(st, t, f);
 }
 
 // D <- last iterate (converted to the storage type), or 0 / I for the special

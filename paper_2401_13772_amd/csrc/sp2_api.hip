@@ -148,6 +148,21 @@ size_t sp2_workspace_size(int n, sp2_dtype dtype, sp2_compute compute) {
 int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, int max_iter,
                 sp2_dtype dtype, sp2_compute compute, int fp64_prefix_iters, void* workspace,
                 size_t workspace_bytes, void* hip_stream, sp2_info* info) {
+    return sp2::density_impl(H, D, n, ld, n_occ, tol, max_iter, dtype, compute, fp64_prefix_iters,
+                             workspace, workspace_bytes, hip_stream, info, false);
+}
+
+}  // extern "C"
+
+namespace sp2 {
+
+// The solve behind sp2_density and sp2_density_noalloc.  no_alloc: no pinned
+// host buffers, events or other allocations; every one of the max_iter steps
+// is queued (steps after the stop return at their first instruction) and the
+// loop state is copied back once at the end into a thread-local host struct.
+int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, int max_iter,
+                 sp2_dtype dtype, sp2_compute compute, int fp64_prefix_iters, void* workspace,
+                 size_t workspace_bytes, void* hip_stream, sp2_info* info, bool no_alloc) {
     if (!H || !D || n <= 0 || n > 65536 || ld < n || n_occ < 0 || n_occ > n)
         return fail(info, SP2_E_INVALID);
     if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 0 || max_iter > SP2_MAX_ITER)
@@ -179,10 +194,12 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
     uint16_t* p1 = (uint16_t*)(ws + L.off_p1);
 
     HostSlots* hs = nullptr;
-    SP2_HIP(slots_for_current(&hs));
     Profile* prof = nullptr;
-    SP2_HIP(profile_for_current(&prof));
-    const bool timed = prof->on;
+    if (!no_alloc) {
+        SP2_HIP(slots_for_current(&hs));
+        SP2_HIP(profile_for_current(&prof));
+    }
+    const bool timed = prof && prof->on;
 
     SP2_HIP(launch_reset(st, n, n_occ, tol, max_iter, m0, cnt, L.max_groups + 2, s));
     SP2_HIP(launch_bounds(H, dtype, n, ld, L, st, rowpart, part, s));
@@ -201,21 +218,20 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
             uint16_t* pn = odd ? p0 : p1;
             hipEvent_t* ev = timed ? &prof->ev[2 * kLaunchesPerStep * issued] : nullptr;
             if (mixed && issued >= m0) {
-                // every launch below checks the device state and runs only if the
-                // step is due in its phase, so exactly one of the two step kernels
-                // does the work
+                // Both step kernels check the device state: exactly one of them
+                // does step `issued` (the split kernel in the split phase, the
+                // FP64 kernel otherwise).  On the first refinement step the
+                // split kernel decodes the planes into the FP64 iterate first.
                 if (issued == m0) SP2_HIP(launch_f64_to_planes(L, compute, xc, pc, st, issued, s));
-                SP2_HIP(launch_planes_to_f64(L, compute, pc, xc, st, issued, s));
+                if (timed) SP2_HIP(hipEventRecord(ev[2], s));
+                SP2_HIP(launch_syrk_lp(L, compute, pc, pn, xc, st, part, scratch, cnt, issued, s));
+                if (timed) SP2_HIP(hipEventRecord(ev[3], s));
             }
             if (timed) SP2_HIP(hipEventRecord(ev[0], s));
             SP2_HIP(launch_syrk_f64(L, xc, xn, st, part, scratch, cnt, issued, s));
             if (timed) SP2_HIP(hipEventRecord(ev[1], s));
-            if (mixed && issued >= m0) {
-                if (timed) SP2_HIP(hipEventRecord(ev[2], s));
-                SP2_HIP(launch_syrk_lp(L, compute, pc, pn, st, part, scratch, cnt, issued, s));
-                if (timed) SP2_HIP(hipEventRecord(ev[3], s));
-            }
         }
+        if (no_alloc) continue;
         SP2_HIP(hipMemcpyAsync(&hs->flags[slot], &st->done, sizeof(int), hipMemcpyDeviceToHost, s));
         SP2_HIP(hipEventRecord(hs->ev[slot], s));
         if (pending >= 0) {
@@ -226,10 +242,12 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
         slot ^= 1;
     }
     SP2_HIP(launch_finalize(D, dtype, n, ld, L, compute, st, x0, x1, p0, p1, s));
-    SP2_HIP(hipMemcpyAsync(hs->state, st, sizeof(State), hipMemcpyDeviceToHost, s));
+    static thread_local State t_state;   // pageable: the no-allocation path
+    State* hstate = no_alloc ? &t_state : hs->state;
+    SP2_HIP(hipMemcpyAsync(hstate, st, sizeof(State), hipMemcpyDeviceToHost, s));
     SP2_HIP(hipStreamSynchronize(s));
 
-    const State& h = *hs->state;
+    const State& h = *hstate;
     if (timed) {
         prof->last_ms[0] = prof->last_ms[1] = 0.0;
         prof->last_steps[0] = prof->last_steps[1] = 0;
@@ -258,6 +276,10 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
     }
     return h.status;
 }
+
+}  // namespace sp2
+
+extern "C" {
 
 int sp2_profile_enable(int on) {
     int dev = 0;

@@ -59,25 +59,32 @@ __device__ inline bool group_arrive_last(unsigned* ticket, unsigned nblocks, int
 
 // ---------------------------------------------------------------- split planes
 // A value x (|x| <= 1 for SP2 iterates) is kept as a sum of 16-bit planes:
-//   F16X2 : x ~ h + l,        h = fp16(x), l = fp16(x - h)      (~6e-8 absolute)
-//   BF16X3: x ~ b1 + b2 + b3, each plane bf16 of the remainder   (~24 bits)
-//   BF16X2: x ~ b1 + b2                                        (~16 bits)
-// Products use hi*hi + hi*lo + lo*hi (+ the next order for BF16X3); the
-// dropped terms are below the FP32 accumulation error.
+//   F16X2 : x ~ h + 2^-11 l',  h = fp16(x), l' = fp16((x - h) 2^11)
+//           (Ootomo & Yokota's split-FP16 form: scaling the residual keeps it
+//           out of FP16's subnormal range, ~22 significant bits for |x| down
+//           to 2^-14 and an absolute quantum of 2^-35 below);
+//   BF16X3: x ~ b1 + b2 + b3, each plane bf16 of the remainder (~24 bits);
+//   BF16X2: x ~ b1 + b2                                      (~16 bits).
+// Products: the leading term hi*hi is accumulated apart from the correction
+// terms (hi*lo + lo*hi, and for BF16X3 the next order), because it alone is
+// O(|S|) and sets the FP32 rounding level; see syrk_lp.hip.  LO_SCALE is the
+// factor that multiplies the correction sum.
 
 template <int MODE> struct Planes;
 
 template <> struct Planes<SP2_C_F16X2> {
     static constexpr int NP = 2;
+    static constexpr double LO_SCALE = 1.0 / 2048.0;
     typedef _Float16 T;
     __device__ static inline void encode(double x, uint16_t* out) {
         const _Float16 h = (_Float16)x;
-        const _Float16 l = (_Float16)(x - (double)h);
+        const _Float16 l = (_Float16)((x - (double)h) * 2048.0);
         out[0] = __builtin_bit_cast(uint16_t, h);
         out[1] = __builtin_bit_cast(uint16_t, l);
     }
     __device__ static inline double decode(const uint16_t* in) {
-        return (double)__builtin_bit_cast(_Float16, in[0]) + (double)__builtin_bit_cast(_Float16, in[1]);
+        return (double)__builtin_bit_cast(_Float16, in[0]) +
+               (double)__builtin_bit_cast(_Float16, in[1]) * (1.0 / 2048.0);
     }
 };
 
@@ -85,6 +92,7 @@ __device__ inline __bf16 to_bf16(double x) { return (__bf16)(float)x; }
 
 template <> struct Planes<SP2_C_BF16X3> {
     static constexpr int NP = 3;
+    static constexpr double LO_SCALE = 1.0;
     typedef __bf16 T;
     __device__ static inline void encode(double x, uint16_t* out) {
         const __bf16 b1 = to_bf16(x);
@@ -104,6 +112,7 @@ template <> struct Planes<SP2_C_BF16X3> {
 
 template <> struct Planes<SP2_C_BF16X2> {
     static constexpr int NP = 2;
+    static constexpr double LO_SCALE = 1.0;
     typedef __bf16 T;
     __device__ static inline void encode(double x, uint16_t* out) {
         const __bf16 b1 = to_bf16(x);
@@ -135,6 +144,103 @@ __device__ inline double load_planes(const uint16_t* base, size_t pstride, size_
     return Planes<MODE>::decode(v);
 }
 
+// ---------------------------------------------------------------- loop state
+// Start of a solve (one thread).
+__device__ inline void state_reset(State* st, int n, int n_occ, double tol, int max_iter, int m0) {
+    st->emin = 0.0;
+    st->emax = 0.0;
+    st->tr = 0.0;
+    st->fro2 = 0.0;
+    st->idem = 0.0;
+    st->tol = tol;
+    st->nocc = (double)n_occ;
+    st->n = n;
+    st->max_iter = max_iter;
+    st->grow = 0;
+    st->done = 0;
+    st->status = SP2_E_NOT_CONVERGED;
+    st->iterations = 0;
+    st->special = 0;
+    st->bad = 0;
+    st->ticket = 0;
+    st->fp64_steps = 0;
+    st->branch_mask[0] = 0;
+    st->branch_mask[1] = 0;
+    st->lp_mask[0] = 0;
+    st->lp_mask[1] = 0;
+    st->phase = 0;
+    st->m0 = m0;
+    st->lp_start = 0;
+    st->lp_steps = 0;
+    st->refine_steps = 0;
+    st->max_refine = 8;
+    st->stale = 0;
+    st->pad0 = 0;
+    st->lp_switch = 0.0;
+    st->n_layers = 0;
+    st->pad1 = 0;
+    st->idem_fallback = 0.0;
+}
+
+// Start of a learned-expansion solve: n_layers trained layers, then one SP2
+// step whose idempotency decides between OK and SP2_E_FALLBACK.
+__device__ inline void state_reset_learned(State* st, int n, int n_occ, double tol, int n_layers,
+                                           double idem_fallback) {
+    state_reset(st, n, n_occ, tol, n_layers + 1, 0);
+    st->n_layers = n_layers;
+    st->idem_fallback = idem_fallback;
+    st->phase = n_layers > 0 ? 3 : 4;
+}
+
+// Coefficients of the update X' = al S + be X + ga I of a learned layer with
+// f(x) = a x^2 + b x + c: the plain map when the trace is above n_occ, the
+// particle-hole form I - f(I - X) = -a S + (2a + b) X + (1 - a - b - c) I
+// otherwise (grow = 1, the branch SP2 sends to 2X - X^2).
+__device__ inline void learned_update_coefs(const double* abc, int grow, double& al, double& be,
+                                            double& ga) {
+    const double a = abc[0], b = abc[1], c = abc[2];
+    if (grow) {
+        al = -a;
+        be = 2.0 * a + b;
+        ga = 1.0 - a - b - c;
+    } else {
+        al = a;
+        be = b;
+        ga = c;
+    }
+}
+
+// After the bounds and X_0 sums (one thread): the trace decides the first
+// branch; special occupations, non-finite input, a degenerate spectrum and
+// max_iter == 0 end the solve before the first squaring.
+__device__ inline void state_after_init(State* st, double t, double f) {
+    st->tr = t;
+    st->fro2 = f;
+    st->grow = (t - st->nocc <= 0.0) ? 1 : 0;
+    const int nn = st->n;
+    if (st->bad) {
+        st->status = SP2_E_INVALID;
+        st->done = 1;
+    } else if (st->nocc == 0.0) {
+        st->special = 1;
+        st->status = SP2_OK;
+        st->done = 1;
+        st->tr = 0.0;
+    } else if (st->nocc == (double)nn) {
+        st->special = 2;
+        st->status = SP2_OK;
+        st->done = 1;
+        st->tr = (double)nn;
+    } else if (!(st->emax > st->emin)) {
+        st->status = SP2_E_DEGENERATE;
+        st->done = 1;
+    } else if (st->max_iter == 0) {
+        st->status = SP2_E_NOT_CONVERGED;
+        st->done = 1;
+    }
+    st->ticket = 0;
+}
+
 // ---------------------------------------------------------------- steering
 // Run by one thread of the last-arriving workgroup after step m, with the
 // fixed-order sums E = ||S - X_m||^2, TR = tr X_{m+1}, F = ||X_{m+1}||^2.
@@ -146,7 +252,7 @@ __device__ inline double load_planes(const uint16_t* base, size_t pstride, size_
 //   phase 2: FP64 refinement: x^2 and 2x - x^2 alternate regardless of the
 //            trace (a trace-steered continuation of a low-precision iterate
 //            can square an eigenvalue at 1 + eps away from 1), until e <= tol.
-__device__ inline void sp2_steer_thread0(State* st, double E, double TR, double F, int grow) {
+__device__ __forceinline__ void sp2_steer_thread0(State* st, double E, double TR, double F, int grow) {
     const int m = st->iterations;
     const double e = sqrt(E);
     st->tr_hist[m] = st->tr;
@@ -191,6 +297,21 @@ __device__ inline void sp2_steer_thread0(State* st, double E, double TR, double 
             st->status = SP2_E_NOT_CONVERGED;
             st->stale = 1;
         }
+    } else if (phase == 3) {
+        // trained layers: steered by the trace, no stop test but convergence
+        st->grow = trace_grow;
+        if (e <= st->tol) {
+            st->done = 1;
+            st->status = SP2_OK;
+        } else if (m + 1 >= st->n_layers) {
+            st->phase = 4;
+        }
+    } else if (phase == 4) {
+        // the SP2 check step: e is the idempotency of the last layer's output
+        st->grow = trace_grow;
+        st->done = 1;
+        const double terr = fabs(TR - st->nocc);
+        st->status = (e <= st->idem_fallback && terr <= st->idem_fallback) ? SP2_OK : SP2_E_FALLBACK;
     } else {
         st->stale = 0;
         st->refine_steps = st->refine_steps + 1;

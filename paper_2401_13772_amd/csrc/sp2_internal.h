@@ -43,6 +43,11 @@ struct State {
     int32_t stale;      // 1: the newest iterate lives only in the split planes
     int32_t pad0;
     double lp_switch;   // leave the split phase once e <= lp_switch
+    // learned expansion: phase 3 = trained layers, phase 4 = the SP2 check
+    // step after them
+    int32_t n_layers;
+    int32_t pad1;
+    double idem_fallback;  // the check step's idempotency bar
     uint64_t branch_mask[2];
     uint64_t lp_mask[2];  // bit m set when step m was a split-operand step
     double tr_hist[SP2_MAX_ITER];
@@ -85,7 +90,9 @@ inline Layout make_layout(int n, sp2_compute compute) {
     size_t init_entries = (size_t)nb * nb * 4;
     if (init_entries > part_entries) part_entries = init_entries;
     int nsplit = (n + kBndColsPerBlock - 1) / kBndColsPerBlock;
-    L.max_groups = L.tiles < kMaxPersistent ? L.tiles : kMaxPersistent;
+    // the 128-tile FP64 kernel runs up to kMaxPersistent workgroups whatever
+    // the tile count (its stream-K remainder spreads a few tiles over many)
+    L.max_groups = (L.bt == 128 || L.tiles > kMaxPersistent) ? kMaxPersistent : L.tiles;
     size_t off = 0;
     L.off_state = off;   off = align_up(off + sizeof(State), 256);
     L.off_part = off;    off = align_up(off + part_entries * sizeof(double), 256);
@@ -93,7 +100,7 @@ inline Layout make_layout(int n, sp2_compute compute) {
     size_t scratch_f64 = 2 * (size_t)(L.max_groups + 1) * L.bt * L.bt * sizeof(double);
     int Tl = L.ldp / kLpTile;
     int lp_groups = Tl * (Tl + 1) / 2 < kMaxPersistent ? Tl * (Tl + 1) / 2 : kMaxPersistent;
-    size_t scratch_lp = L.np ? 2 * (size_t)(lp_groups + 1) * kLpTile * kLpTile * sizeof(float) : 0;
+    size_t scratch_lp = L.np ? 2 * (size_t)(lp_groups + 1) * kLpTile * kLpTile * sizeof(double) : 0;
     if (L.np && lp_groups > L.max_groups) L.max_groups = lp_groups;
     L.off_cnt = off;     off = align_up(off + (size_t)(L.max_groups + 2) * sizeof(unsigned), 256);
     L.off_scratch = off; off = align_up(off + (scratch_f64 > scratch_lp ? scratch_f64 : scratch_lp), 256);
@@ -154,6 +161,18 @@ __device__ inline bool arrive_last(State* st, unsigned nblocks, int* flag_lds) {
     return last;
 }
 
+// ---------------------------------------------------------------- host side
+
+// The solve behind sp2_density (and its no-allocation variant); see sp2_api.hip.
+int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, int max_iter,
+                 sp2_dtype dtype, sp2_compute compute, int fp64_prefix_iters, void* workspace,
+                 size_t workspace_bytes, void* hip_stream, sp2_info* info, bool no_alloc);
+
+// The batched plan behind sp2_plan_create and the learned expansion (sp2_batch.hip).
+int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ, sp2_dtype dtype,
+                     sp2_compute compute, double tol, int max_iter, const char* autotune_cache,
+                     const double* coef, int n_layers, double idem_fallback);
+
 // ---------------------------------------------------------------- host launchers
 
 hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, int m0,
@@ -165,10 +184,8 @@ hipError_t launch_init(const void* H, sp2_dtype dt, int n, int ld, const Layout&
 hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* st, double* part,
                            double* scratch, unsigned* cnt, int step, hipStream_t s);
 hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const uint16_t* Pin, uint16_t* Pout,
-                          State* st, double* part, void* scratch, unsigned* cnt, int step,
-                          hipStream_t s);
-hipError_t launch_planes_to_f64(const Layout& L, sp2_compute mode, const uint16_t* Pin, double* X,
-                                const State* st, int step, hipStream_t s);
+                          double* X, State* st, double* part, double* scratch, unsigned* cnt,
+                          int step, hipStream_t s);
 hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, uint16_t* Pout,
                                 const State* st, int step, hipStream_t s);
 hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, sp2_compute mode,

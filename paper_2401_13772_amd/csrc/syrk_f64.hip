@@ -32,147 +32,9 @@
 //     in that XCD's L2;
 //   * per-tile sums go to a partial buffer that the last-arriving workgroup
 //     adds in tile order: deterministic, no floating-point atomics.
-#include "sp2_device.h"
+#include "syrk_f64_core.h"
 
 namespace sp2 {
-
-constexpr int kBK = 16;
-constexpr int kLDK = kBK + 1;
-
-template <int BT_, int WM_, int WN_>
-struct SyrkCfg {
-    static constexpr int BT = BT_, WM = WM_, WN = WN_;
-    static constexpr int NT = 64 * WM * WN;          // threads per workgroup
-    static constexpr int NW = WM * WN;               // waves per workgroup
-    static constexpr int WTM = BT / WM, WTN = BT / WN;
-    static constexpr int MI = WTM / 16, NI = WTN / 16;
-    static constexpr int LOADS = BT * kBK / 2 / NT;  // double2 chunks per thread per panel
-    static constexpr size_t LDS = (size_t)2 * 2 * BT * kLDK * sizeof(double);
-    static_assert(LOADS >= 1 && (BT * kBK / 2) % NT == 0, "panel slice must split evenly");
-};
-
-using CfgSmall = SyrkCfg<64, 2, 2>;    // 256 threads, 32 x 32 per wave
-using CfgLarge = SyrkCfg<128, 2, 4>;   // 512 threads, 64 x 32 per wave
-
-// Accumulate the C tile over K slices [kt0, kt1) of the row panels of tiles
-// ti and tj.  DIAG: ti == tj, both operands come from one panel.
-template <class C, bool DIAG>
-__device__ __forceinline__ void syrk_mainloop(const double* __restrict__ X, int ldp, int ti, int tj,
-                                              int kt0, int kt1, double* sA, double* sB,
-                                              d4 (&acc)[C::MI][C::NI]) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w / C::WN, wn = w % C::WN;
-    const double* Ap = X + (size_t)ti * C::BT * ldp;
-    const double* Bp = X + (size_t)tj * C::BT * ldp;
-    int goff[C::LOADS], soff[C::LOADS];
-#pragma unroll
-    for (int i = 0; i < C::LOADS; ++i) {
-        const int c = tid + C::NT * i;
-        const int row = c >> 3, kk = (c & 7) * 2;
-        goff[i] = row * ldp + kk;
-        soff[i] = row * kLDK + kk;
-    }
-    d2 ra[C::LOADS], rb[C::LOADS];
-#pragma unroll
-    for (int i = 0; i < C::LOADS; ++i) {
-        ra[i] = *(const d2*)(Ap + goff[i] + kt0 * kBK);
-        if (!DIAG) rb[i] = *(const d2*)(Bp + goff[i] + kt0 * kBK);
-    }
-#pragma unroll
-    for (int i = 0; i < C::LOADS; ++i) {
-        sA[soff[i]] = ra[i].x;
-        sA[soff[i] + 1] = ra[i].y;
-        if (!DIAG) {
-            sB[soff[i]] = rb[i].x;
-            sB[soff[i] + 1] = rb[i].y;
-        }
-    }
-    __syncthreads();
-    const int arow = (wm * C::WTM + (lane & 15)) * kLDK + (lane >> 4);
-    const int brow = (wn * C::WTN + (lane & 15)) * kLDK + (lane >> 4);
-    for (int kt = kt0; kt < kt1; ++kt) {
-        const int stg = (kt - kt0) & 1;
-        const bool more = kt + 1 < kt1;
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < C::LOADS; ++i) {
-                ra[i] = *(const d2*)(Ap + goff[i] + (kt + 1) * kBK);
-                if (!DIAG) rb[i] = *(const d2*)(Bp + goff[i] + (kt + 1) * kBK);
-            }
-        }
-        const double* a = sA + stg * C::BT * kLDK;
-        const double* b = DIAG ? a : (sB + stg * C::BT * kLDK);
-#pragma unroll
-        for (int s = 0; s < kBK / 4; ++s) {
-            double af[C::MI], bf[C::NI];
-#pragma unroll
-            for (int mi = 0; mi < C::MI; ++mi) af[mi] = a[arow + mi * 16 * kLDK + 4 * s];
-#pragma unroll
-            for (int ni = 0; ni < C::NI; ++ni) bf[ni] = b[brow + ni * 16 * kLDK + 4 * s];
-#pragma unroll
-            for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < C::NI; ++ni)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
-        }
-        if (more) {
-            double* na = sA + (stg ^ 1) * C::BT * kLDK;
-            double* nb = sB + (stg ^ 1) * C::BT * kLDK;
-#pragma unroll
-            for (int i = 0; i < C::LOADS; ++i) {
-                na[soff[i]] = ra[i].x;
-                na[soff[i] + 1] = ra[i].y;
-                if (!DIAG) {
-                    nb[soff[i]] = rb[i].x;
-                    nb[soff[i] + 1] = rb[i].y;
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// The SP2 update of one finished C tile, and this thread's share of the
-// tile's e^2, trace and ||X'||^2.
-// Accumulator layout of v_mfma_f64_16x16x4f64 (checked on gfx950): lane l
-// holds column l%16 of the 16x16 block at rows l/16 + 4r, r = 0..3.  For a
-// fixed r the 64 lanes cover 4 rows x 16 consecutive columns, so the direct
-// reads and writes are 128-byte row segments.
-template <class C>
-__device__ __forceinline__ void sp2_epilogue(const double* __restrict__ X, double* __restrict__ Y,
-                                             int ldp, int ti, int tj, int grow,
-                                             const d4 (&acc)[C::MI][C::NI], double& e2,
-                                             double& trp, double& fro) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w / C::WN, wn = w % C::WN;
-    const bool diag = (ti == tj);
-#pragma unroll
-    for (int mi = 0; mi < C::MI; ++mi) {
-#pragma unroll
-        for (int ni = 0; ni < C::NI; ++ni) {
-            const int gi0 = ti * C::BT + wm * C::WTM + mi * 16 + (lane >> 4);
-            const int gj = tj * C::BT + wn * C::WTN + ni * 16 + (lane & 15);
-            double xv[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) xv[r] = X[(size_t)(gi0 + 4 * r) * ldp + gj];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gi = gi0 + 4 * r;
-                const double s = acc[mi][ni][r];
-                const double x = xv[r];
-                const double d = s - x;
-                const double xn = grow ? (2.0 * x - s) : s;
-                const double wgt = (gi > gj) ? 2.0 : ((gi == gj) ? 1.0 : 0.0);
-                e2 += wgt * (d * d);
-                fro += wgt * (xn * xn);
-                if (gi == gj) trp += xn;
-                // lower copy; the upper copy mirrors it (diagonal tiles: lower half wins)
-                if (!diag || gi >= gj) Y[(size_t)gi * ldp + gj] = xn;
-                if (!diag || gi > gj) Y[(size_t)gj * ldp + gi] = xn;
-            }
-        }
-    }
-}
 
 // Stream-K SYRK + SP2 step.  grid = G persistent workgroups (G <= ntiles).
 // scratch: 2 (G + 1) C-tile partials; cnt: G + 1 arrival counters, zero on
@@ -271,6 +133,179 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64(const double* __restrict__ X
     if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
 }
 
+// ---------------------------------------------------------------- 128-tile kernel
+// Data-parallel waves plus a stream-K remainder.  With G co-resident
+// workgroups and N lower tiles, the first floor(N/G) * G tiles (grouped
+// raster order) go out in whole waves: every workgroup starts its tile at
+// K = 0 at the same time, so the workgroups of one XCD (a contiguous run of
+// the order) stream the same row and column panels through its L2 together.
+// The R = N mod G tiles left over are split evenly over all G workgroups as
+// contiguous ranges of K slices (a range is shorter than a tile, so it touches
+// at most two tiles).  Each segment of a split tile is stored as an FP64
+// partial in slot 2g (the workgroup's first tile) or 2g + 1 (its second); the
+// last of the tile's segments to arrive adds all of them in workgroup order
+// and runs the epilogue.  The sum does not depend on arrival order.
+constexpr int kGroupM = 8;
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_syrk_f64_hyb(const double* __restrict__ X, double* __restrict__ Y,
+                                                        int ldp, int T, State* st, double* __restrict__ part,
+                                                        double* __restrict__ scratch,
+                                                        unsigned* __restrict__ cnt, int step) {
+    extern __shared__ __attribute__((aligned(16))) char lsm[];
+    __shared__ double red[C::NW];
+    __shared__ int flag;
+
+    if (st->done || st->iterations != step || st->phase == 1) return;
+    const int grow = st->grow;
+    const unsigned G = gridDim.x;
+    const unsigned g = xcd_remap(blockIdx.x, G);
+    const int KT = ldp / kBK;
+    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
+    const unsigned waves = ntiles / G;
+    const unsigned Dt = waves * G;
+    const unsigned R = ntiles - Dt;
+    const int tid = threadIdx.x;
+
+    auto finish = [&](unsigned t, int ti, int tj, d4 (&acc)[C::MI][C::NI]) {
+        double e2 = 0.0, trp = 0.0, fro = 0.0;
+        sp2_epilogue_lds<C>(X, Y, ldp, ti, tj, grow, acc, (double*)lsm, e2, trp, fro);
+        e2 = group_sum<C::NW>(e2, red);
+        trp = group_sum<C::NW>(trp, red);
+        fro = group_sum<C::NW>(fro, red);
+        if (tid == 0) {
+            part[4 * t + 0] = e2;
+            part[4 * t + 1] = trp;
+            part[4 * t + 2] = fro;
+        }
+    };
+
+    // data-parallel waves
+    for (unsigned w = 0; w < waves; ++w) {
+        const unsigned t = w * G + g;
+        int ti, tj;
+        grouped_tile(t, T, kGroupM, ti, tj);
+        d4 acc[C::MI][C::NI];
+#pragma unroll
+        for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+        if (ti == tj) syrk_mainloop_dma<C, true>(X, ldp, ti, tj, 0, KT, lsm, acc);
+        else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, 0, KT, lsm, acc);
+        finish(t, ti, tj, acc);
+    }
+
+    // stream-K remainder: the R * KT remainder slices over the first Gs
+    // workgroups, every range non-empty and at least KT/16 long (a tile has
+    // at most 16 segments to add).  R < G <= 1024 and KT <= 4096 keep every
+    // product below 2^32, so the range arithmetic is 32-bit.
+    if (R > 0) {
+        const unsigned U = R * (unsigned)KT;
+        const unsigned minr = KT >= 16 ? (unsigned)KT / 16u : 1u;
+        const unsigned Gs = (U / minr < G) ? (U / minr > 0 ? U / minr : 1u) : G;
+        const unsigned u0 = g < Gs ? (U * g) / Gs : U;
+        const unsigned u1 = g < Gs ? (U * (g + 1)) / Gs : U;
+        unsigned u = u0;
+        int seg_no = 0;
+        while (u < u1) {
+            const unsigned r = u / (unsigned)KT;
+            const int k0 = (int)(u - r * (unsigned)KT);
+            const unsigned kend = (unsigned)k0 + (u1 - u);
+            const int k1 = kend < (unsigned)KT ? (int)kend : KT;
+            const unsigned t = Dt + r;
+            int ti, tj;
+            grouped_tile(t, T, kGroupM, ti, tj);
+            d4 acc[C::MI][C::NI];
+#pragma unroll
+            for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+            if (ti == tj) syrk_mainloop_dma<C, true>(X, ldp, ti, tj, k0, k1, lsm, acc);
+            else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, k0, k1, lsm, acc);
+            u += (unsigned)(k1 - k0);
+            const int slot = seg_no++;
+            if (k0 == 0 && k1 == KT) {        // a whole tile in one range
+                finish(t, ti, tj, acc);
+                continue;
+            }
+            // owners of the tile's first and last slice: the workgroups q
+            // with (U q)/Gs <= s < (U (q + 1))/Gs
+            const unsigned ts = r * (unsigned)KT, te = ts + (unsigned)KT;
+            const unsigned ga = ((ts + 1) * Gs - 1) / U;
+            const unsigned gb = (te * Gs - 1) / U;
+            const size_t tile_elems = (size_t)C::BT * C::BT;
+            d4* mine = (d4*)(scratch + (2 * (size_t)g + slot) * tile_elems);
+#pragma unroll
+            for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < C::NI; ++ni) mine[(mi * C::NI + ni) * C::NT + tid] = acc[mi][ni];
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) flag = (int)atomicAdd(&cnt[r], 1u);
+            __syncthreads();
+            if (flag != (int)(gb - ga)) continue;    // not the last segment to arrive
+            __threadfence();
+#pragma unroll
+            for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+            for (unsigned q = ga; q <= gb; ++q) {
+                // tile r is q's first tile unless q's range starts in an earlier tile
+                const unsigned qs = ((U * q) / Gs / (unsigned)KT == r) ? 0u : 1u;
+                const d4* o = (const d4*)(scratch + (2 * (size_t)q + qs) * tile_elems);
+#pragma unroll
+                for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] += o[(mi * C::NI + ni) * C::NT + tid];
+            }
+            if (tid == 0) cnt[r] = 0u;
+            finish(t, ti, tj, acc);
+        }
+    }
+
+    if (!group_arrive_last(&st->ticket, G, &flag)) return;
+    double E = 0.0, TR = 0.0, F = 0.0;
+    for (unsigned k = tid; k < ntiles; k += C::NT) {
+        E += part[4 * k + 0];
+        TR += part[4 * k + 1];
+        F += part[4 * k + 2];
+    }
+    E = group_sum<C::NW>(E, red);
+    TR = group_sum<C::NW>(TR, red);
+    F = group_sum<C::NW>(F, red);
+    if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
+}
+
+using CfgHyb = SyrkCfg<128, 2, 2>;   // 256 threads, 64 x 64 per wave, LDS-DMA operands
+
+static hipError_t launch_hyb(const Layout& L, const double* X, double* Y, State* st, double* part,
+                             double* scratch, unsigned* cnt, int step, hipStream_t s) {
+    using C = CfgHyb;
+    constexpr size_t lds = DmaLayout<C>::LDS > LdsEpi<C>::LDS ? DmaLayout<C>::LDS : LdsEpi<C>::LDS;
+    static int per_cu = -1;
+    static int cus = 0;
+    if (per_cu < 0) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_syrk_f64_hyb<C>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        int dev = 0, nb = 0;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_syrk_f64_hyb<C>, C::NT, lds);
+        if (e != hipSuccess) return e;
+        per_cu = nb < 1 ? 1 : nb;
+    }
+    const int T = L.ldp / C::BT;
+    int G = per_cu * cus;
+    if (G > L.max_groups) G = L.max_groups;   // the workspace holds 2 G partial tiles and G counters
+    if (G < 1) G = 1;
+    hipLaunchKernelGGL(k_syrk_f64_hyb<C>, dim3(G), dim3(C::NT), lds, s, X, Y, L.ldp, T, st, part, scratch, cnt,
+                       step);
+    return hipGetLastError();
+}
+
 template <class C>
 static hipError_t launch_cfg(const Layout& L, const double* X, double* Y, State* st, double* part,
                              double* scratch, unsigned* cnt, int step, hipStream_t s) {
@@ -303,7 +338,7 @@ static hipError_t launch_cfg(const Layout& L, const double* X, double* Y, State*
 hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* st, double* part,
                            double* scratch, unsigned* cnt, int step, hipStream_t s) {
     if (L.bt == CfgSmall::BT) return launch_cfg<CfgSmall>(L, X, Y, st, part, scratch, cnt, step, s);
-    return launch_cfg<CfgLarge>(L, X, Y, st, part, scratch, cnt, step, s);
+    return launch_hyb(L, X, Y, st, part, scratch, cnt, step, s);
 }
 
 }  // namespace sp2

@@ -2,18 +2,28 @@
 // matrix cores (the low-precision phase of a mixed-precision solve).
 //
 // The iterate X (|x| <= 1) is held as 16-bit planes (see sp2_device.h):
-// FP16 x2 (h + l), BF16 x3 or BF16 x2.  S = X X^T is formed from the plane
-// products hi*hi + hi*lo + lo*hi (+ the next order for BF16 x3) with
-// v_mfma_f32_16x16x32_{f16,bf16}, accumulated in FP32.  The epilogue is the
-// same SP2 update as the FP64 step (Section "SP2 solver": X' = X^2 or
-// 2X - X^2 by the trace), evaluated in FP64 from the decoded X and the FP32
-// product; it writes the planes of X' (they are the iterate during this
-// phase: no FP64 copy is stored) and the per-tile e^2, trace and ||X'||^2.
-// Steering is taken by the last-arriving workgroup (sp2_steer_thread0).
+// FP16 x2 (h + 2^-11 l'), BF16 x3 or BF16 x2.  S = X X^T is formed from the
+// plane products with v_mfma_f32_16x16x32_{f16,bf16} in two parts:
+//   * the leading term hi*hi.  Each K slice of 32 is one MFMA with a zero
+//     accumulator input, so its FP32 rounding is that of a 32-term sum, and
+//     the slice result is added into an FP64 accumulator.  One long FP32
+//     accumulation over K = n instead rounds every slice against the O(|S|)
+//     running sum, and that error grows with n (at n = 4096 it alone moves
+//     the converged D by ~1e-6 rms);
+//   * the correction terms hi*lo + lo*hi (+ the next order for BF16 x3), in
+//     an FP32 accumulator of their own: they are 2^-11 (2^-8) of |S|, so
+//     their FP32 rounding is far below the plane rounding of X'.
+// S = acc64 + LO_SCALE * acc32.  The epilogue is the same SP2 update as the
+// FP64 step (Section "SP2 solver": X' = X^2 or 2X - X^2 by the trace),
+// evaluated in FP64 from the decoded X and S; it writes the planes of X'
+// (they are the iterate during this phase: no FP64 copy is stored) and the
+// per-tile e^2, trace and ||X'||^2.  Steering is taken by the last-arriving
+// workgroup (sp2_steer_thread0).
 //
 // Design for CDNA4:
-//   * 128 x 128 tiles of the lower block triangle, 4 wave64s each owning
-//     64 x 64 (16 accumulator blocks, one FP32 accumulator per block);
+//   * 128 x 128 tiles of the lower block triangle, 8 wave64s each owning
+//     64 x 32 (4 x 2 blocks of 16 x 16; FP64 + FP32 accumulators = 24 VGPRs
+//     per block);
 //   * operand panels go straight from global memory to LDS with the 16-byte
 //     LDS-DMA load (global_load_lds_dwordx4): no staging registers.  Each
 //     wave instruction fills 1 KiB = 16 rows x 64 B; a row's four 16-byte
@@ -21,7 +31,7 @@
 //     a ds_read_b128 serves per cycle hit distinct banks;
 //   * double-buffered K slices of 32 elements, one barrier per slice;
 //   * the same stream-K schedule, XCD renumbering and order-independent
-//     split-tile fix-up as the FP64 step.
+//     split-tile fix-up as the FP64 step, with FP64 partial tiles.
 #include "sp2_device.h"
 
 namespace sp2 {
@@ -41,12 +51,13 @@ struct LpCfg {
     static constexpr int NP = Planes<MODE>::NP;
     static constexpr int PANEL_BYTES = BT * kLBK * 2;          // one plane of one panel
     static constexpr int STAGE_BYTES = NP * 2 * PANEL_BYTES;
-    static constexpr int CLD = BT + 1;                          // padded row of the LDS C tile (floats)
-    static constexpr size_t CTILE = (size_t)BT * CLD * sizeof(float);
+    static constexpr int CLD = BT + 1;                          // padded row of the LDS S tile (doubles)
+    static constexpr size_t CTILE = (size_t)BT * CLD * sizeof(double);
     static constexpr size_t LDS = 2 * (size_t)STAGE_BYTES > CTILE ? 2 * (size_t)STAGE_BYTES : CTILE;
     static constexpr int BLOCKS = PANEL_BYTES / 1024;           // 1 KiB LDS-DMA blocks per panel plane
     static constexpr int BPW = BLOCKS / NW;                     // ... per wave
     static_assert(BLOCKS % NW == 0, "panel must split evenly over the waves");
+    static_assert(LDS <= 160 * 1024, "LDS budget of one CU");
 };
 
 template <int MODE>
@@ -87,7 +98,7 @@ __device__ __forceinline__ void lp_issue(const uint16_t* __restrict__ P, size_t 
 template <class C, bool DIAG>
 __device__ __forceinline__ void lp_mainloop(const uint16_t* __restrict__ P, size_t pstride, int ldp,
                                             int ti, int tj, int kt0, int kt1, char* smem,
-                                            f4 (&acc)[C::MI][C::NI]) {
+                                            d4 (&acc)[C::MI][C::NI], f4 (&accx)[C::MI][C::NI]) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w / C::WN, wn = w % C::WN;
     const int rowA = ti * C::BT, rowB = tj * C::BT;
@@ -106,6 +117,7 @@ __device__ __forceinline__ void lp_mainloop(const uint16_t* __restrict__ P, size
         const int row = wn * C::WTN + ni * 16 + (lane & 15);
         boff[ni] = row * 64 + (((lane >> 4) ^ swz(row)) << 4);
     }
+    const f4 zero = {0.f, 0.f, 0.f, 0.f};
     for (int kt = kt0; kt < kt1; ++kt) {
         const int stg = (kt - kt0) & 1;
         if (kt + 1 < kt1)
@@ -121,44 +133,44 @@ __device__ __forceinline__ void lp_mainloop(const uint16_t* __restrict__ P, size
 #pragma unroll
             for (int ni = 0; ni < C::NI; ++ni) bf[p][ni] = *(const uint4*)(pb + boff[ni]);
         }
-        // products ordered small to large; each pass touches all blocks before
-        // the next pass reuses an accumulator
+        // correction terms, smallest first, into the FP32 accumulator
         if constexpr (C::NP == 3) {
 #pragma unroll
             for (int mi = 0; mi < C::MI; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[2][mi], bf[0][ni], acc[mi][ni]);
-#pragma unroll
-            for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[1][mi], bf[1][ni], acc[mi][ni]);
-#pragma unroll
-            for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[2][ni], acc[mi][ni]);
+                for (int ni = 0; ni < C::NI; ++ni) {
+                    accx[mi][ni] = mfma16<C::MODE>(af[2][mi], bf[0][ni], accx[mi][ni]);
+                    accx[mi][ni] = mfma16<C::MODE>(af[1][mi], bf[1][ni], accx[mi][ni]);
+                    accx[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[2][ni], accx[mi][ni]);
+                }
         }
 #pragma unroll
         for (int mi = 0; mi < C::MI; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[1][mi], bf[0][ni], acc[mi][ni]);
+            for (int ni = 0; ni < C::NI; ++ni) {
+                accx[mi][ni] = mfma16<C::MODE>(af[1][mi], bf[0][ni], accx[mi][ni]);
+                accx[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[1][ni], accx[mi][ni]);
+            }
+        // leading term: one slice per MFMA, promoted into FP64
 #pragma unroll
         for (int mi = 0; mi < C::MI; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[1][ni], acc[mi][ni]);
-#pragma unroll
-        for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[0][ni], acc[mi][ni]);
+            for (int ni = 0; ni < C::NI; ++ni) {
+                const f4 t = mfma16<C::MODE>(af[0][mi], bf[0][ni], zero);
+                acc[mi][ni] += d4{(double)t[0], (double)t[1], (double)t[2], (double)t[3]};
+            }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
 }
 
-// Accumulators -> padded LDS tile C[BT][BT+1] (floats).  Accumulator layout of
-// v_mfma_f32_16x16x32_{f16,bf16} (checked on gfx950): lane l holds column l%16
-// of the 16x16 block at rows 4*(l/16) + r, r = 0..3.
+// Accumulators -> padded LDS tile S[BT][BT+1] (doubles), S = acc64 + LO_SCALE *
+// acc32.  Accumulator layout of v_mfma_f32_16x16x32_{f16,bf16} (checked on
+// gfx950): lane l holds column l%16 of the 16x16 block at rows 4*(l/16) + r,
+// r = 0..3.
 template <class C>
-__device__ __forceinline__ void lp_acc_to_lds(const f4 (&acc)[C::MI][C::NI], float* Cs) {
+__device__ __forceinline__ void lp_acc_to_lds(const d4 (&acc)[C::MI][C::NI], const f4 (&accx)[C::MI][C::NI],
+                                              double* Cs) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w / C::WN, wn = w % C::WN;
 #pragma unroll
@@ -168,7 +180,8 @@ __device__ __forceinline__ void lp_acc_to_lds(const f4 (&acc)[C::MI][C::NI], flo
             const int r0 = wm * C::WTM + mi * 16 + 4 * (lane >> 4);
             const int c = wn * C::WTN + ni * 16 + (lane & 15);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Cs[(r0 + r) * C::CLD + c] = acc[mi][ni][r];
+            for (int r = 0; r < 4; ++r)
+                Cs[(r0 + r) * C::CLD + c] = acc[mi][ni][r] + Planes<C::MODE>::LO_SCALE * (double)accx[mi][ni][r];
         }
 }
 
@@ -184,7 +197,7 @@ __device__ __forceinline__ void lp_acc_to_lds(const f4 (&acc)[C::MI][C::NI], flo
 template <class C>
 __device__ __forceinline__ void lp_epilogue(const uint16_t* __restrict__ Pin, uint16_t* __restrict__ Pout,
                                             size_t pstride, int ldp, int ti, int tj, int grow,
-                                            const float* Cs, double& e2, double& trp, double& fro) {
+                                            const double* Cs, double& e2, double& trp, double& fro) {
     constexpr int RUN = 8;
     constexpr int RUNS_PER_ROW = C::BT / RUN;
     const bool diag = (ti == tj);
@@ -202,15 +215,14 @@ __device__ __forceinline__ void lp_epilogue(const uint16_t* __restrict__ Pin, ui
             for (int k = 0; k < RUN; ++k) {
                 const int c = c0 + k;
                 // S at (row r, col c) of this pass's tile
-                float sf;
-                if (pass == 1) sf = Cs[c * C::CLD + r];                        // mirrored tile
-                else if (diag && c > r) sf = Cs[c * C::CLD + r];               // upper half of a diagonal tile
-                else sf = Cs[r * C::CLD + c];
+                double sd;
+                if (pass == 1) sd = Cs[c * C::CLD + r];                        // mirrored tile
+                else if (diag && c > r) sd = Cs[c * C::CLD + r];               // upper half of a diagonal tile
+                else sd = Cs[r * C::CLD + c];
                 uint16_t v[C::NP];
 #pragma unroll
                 for (int p = 0; p < C::NP; ++p) v[p] = xin[p][k];
                 const double x = Planes<C::MODE>::decode(v);
-                const double sd = (double)sf;
                 const double xn = grow ? (2.0 * x - sd) : sd;
                 if (pass == 0) {
                     const double d = sd - x;
@@ -230,20 +242,33 @@ __device__ __forceinline__ void lp_epilogue(const uint16_t* __restrict__ Pin, ui
     }
 }
 
-// Stream-K split-operand step (phase 1 only).  `step` is the index of the
-// step this launch performs; it does nothing unless the loop state says that
-// step is due and in the split-precision phase.
+// Stream-K split-operand step.  `step` is the index of the step this launch
+// performs.  In the split-precision phase it does that step.  On the step
+// where the loop has just handed over to the FP64 refinement (phase 2 with
+// the iterate only in planes), it instead decodes the planes into the FP64
+// iterate X that the FP64 step launched next reads.  Otherwise it returns at
+// once.
 template <class C>
 __global__ __launch_bounds__(C::NT) void k_syrk_lp(const uint16_t* __restrict__ Pin,
                                                    uint16_t* __restrict__ Pout, size_t pstride,
-                                                   int ldp, int T, State* st, double* __restrict__ part,
-                                                   float* __restrict__ scratch,
+                                                   double* __restrict__ X, int ldp, int T, State* st,
+                                                   double* __restrict__ part,
+                                                   double* __restrict__ scratch,
                                                    unsigned* __restrict__ cnt, int step) {
     extern __shared__ __attribute__((aligned(16))) char lsmem[];
     __shared__ double red[C::NW];
     __shared__ int flag;
 
-    if (st->done || st->iterations != step || st->phase != 1) return;
+    if (st->done || st->iterations != step) return;
+    const int phase = st->phase;
+    if (phase == 2) {
+        if (!st->stale) return;
+        const size_t count = (size_t)ldp * ldp;
+        for (size_t i = (size_t)blockIdx.x * C::NT + threadIdx.x; i < count; i += (size_t)gridDim.x * C::NT)
+            X[i] = load_planes<C::MODE>(Pin, pstride, i);
+        return;
+    }
+    if (phase != 1) return;
     const int grow = st->grow;
     const unsigned G = gridDim.x;
     const unsigned g = xcd_remap(blockIdx.x, G);
@@ -261,17 +286,21 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const uint16_t* __restrict__ 
         const int k1 = kend < (uint64_t)KT ? (int)kend : KT;
         int ti, tj;
         tri_tile(t, ti, tj);
-        f4 acc[C::MI][C::NI];
+        d4 acc[C::MI][C::NI];
+        f4 accx[C::MI][C::NI];
 #pragma unroll
         for (int mi = 0; mi < C::MI; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
-        if (ti == tj) lp_mainloop<C, true>(Pin, pstride, ldp, ti, tj, k0, k1, lsmem, acc);
-        else lp_mainloop<C, false>(Pin, pstride, ldp, ti, tj, k0, k1, lsmem, acc);
+            for (int ni = 0; ni < C::NI; ++ni) {
+                acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+                accx[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+            }
+        if (ti == tj) lp_mainloop<C, true>(Pin, pstride, ldp, ti, tj, k0, k1, lsmem, acc, accx);
+        else lp_mainloop<C, false>(Pin, pstride, ldp, ti, tj, k0, k1, lsmem, acc, accx);
         u += (uint64_t)(k1 - k0);
 
-        float* Cs = (float*)lsmem;       // the stage buffers are free after the main loop
-        lp_acc_to_lds<C>(acc, Cs);
+        double* Cs = (double*)lsmem;     // the stage buffers are free after the main loop
+        lp_acc_to_lds<C>(acc, accx, Cs);
         __syncthreads();
         if (!(k0 == 0 && k1 == KT)) {
             // split tile: seg 0 = [0, kb) ends at this group's range end
@@ -279,8 +308,8 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const uint16_t* __restrict__ 
             const int seg = (k0 == 0) ? 0 : 1;
             const unsigned bidx = (seg == 0) ? g + 1 : g;
             const size_t tile_elems = (size_t)C::BT * C::BT;
-            float* mine = scratch + (2 * (size_t)bidx + seg) * tile_elems;
-            const float* other = scratch + (2 * (size_t)bidx + (1 - seg)) * tile_elems;
+            double* mine = scratch + (2 * (size_t)bidx + seg) * tile_elems;
+            const double* other = scratch + (2 * (size_t)bidx + (1 - seg)) * tile_elems;
             for (int i = tid; i < C::BT * C::BT; i += C::NT)
                 mine[i] = Cs[(i / C::BT) * C::CLD + (i % C::BT)];
             __threadfence();
@@ -290,8 +319,8 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const uint16_t* __restrict__ 
             if (flag == 0) continue;             // the other segment will finish the tile
             __threadfence();
             for (int i = tid; i < C::BT * C::BT; i += C::NT) {
-                float* c = &Cs[(i / C::BT) * C::CLD + (i % C::BT)];
-                const float o = other[i];
+                double* c = &Cs[(i / C::BT) * C::CLD + (i % C::BT)];
+                const double o = other[i];
                 *c = (seg == 0) ? (*c + o) : (o + *c);
             }
             if (tid == 0) cnt[bidx] = 0u;
@@ -322,18 +351,6 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const uint16_t* __restrict__ 
     if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
 }
 
-// The FP64 iterate from its planes, once, when the split-precision phase
-// hands over to the FP64 refinement (step `step`).
-template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_planes_to_f64(const uint16_t* __restrict__ Pin,
-                                                            size_t pstride, double* __restrict__ X,
-                                                            size_t count, const State* st, int step) {
-    if (st->done || st->iterations != step || st->phase != 2 || !st->stale) return;
-    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < count;
-         i += (size_t)gridDim.x * kThreads)
-        X[i] = load_planes<MODE>(Pin, pstride, i);
-}
-
 // The planes of the FP64 iterate, once, when the FP64 prefix hands over to the
 // split-precision phase (at the start of step `step` = m0).
 template <int MODE>
@@ -347,8 +364,9 @@ __global__ __launch_bounds__(kThreads) void k_f64_to_planes(const double* __rest
 }
 
 template <class C>
-static hipError_t launch_lp_cfg(const Layout& L, const uint16_t* Pin, uint16_t* Pout, State* st,
-                                double* part, float* scratch, unsigned* cnt, int step, hipStream_t s) {
+static hipError_t launch_lp_cfg(const Layout& L, const uint16_t* Pin, uint16_t* Pout, double* X,
+                                State* st, double* part, double* scratch, unsigned* cnt, int step,
+                                hipStream_t s) {
     static int per_cu = -1;
     static int cus = 0;
     if (per_cu < 0) {
@@ -370,48 +388,27 @@ static hipError_t launch_lp_cfg(const Layout& L, const uint16_t* Pin, uint16_t* 
     if (G > kMaxPersistent) G = kMaxPersistent;
     if (G > ntiles) G = ntiles;
     if (G < 1) G = 1;
-    hipLaunchKernelGGL(k_syrk_lp<C>, dim3(G), dim3(C::NT), C::LDS, s, Pin, Pout, L.plane_stride, L.ldp,
-                       T, st, part, scratch, cnt, step);
+    hipLaunchKernelGGL(k_syrk_lp<C>, dim3(G), dim3(C::NT), C::LDS, s, Pin, Pout, L.plane_stride, X,
+                       L.ldp, T, st, part, scratch, cnt, step);
     return hipGetLastError();
 }
+
+// 8 waves of 64 x 32: two FP64 + one FP32 accumulator sets fit the VGPR budget
+template <int MODE> using LpMain = LpCfg<kLpTile, 2, 4, MODE>;
 
 hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const uint16_t* Pin, uint16_t* Pout,
-                          State* st, double* part, void* scratch, unsigned* cnt, int step,
-                          hipStream_t s) {
-    float* sc = (float*)scratch;
+                          double* X, State* st, double* part, double* scratch, unsigned* cnt,
+                          int step, hipStream_t s) {
     switch (mode) {
         case SP2_C_F16X2:
-            return launch_lp_cfg<LpCfg<128, 2, 2, SP2_C_F16X2>>(L, Pin, Pout, st, part, sc, cnt, step, s);
+            return launch_lp_cfg<LpMain<SP2_C_F16X2>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
         case SP2_C_BF16X3:
-            return launch_lp_cfg<LpCfg<128, 2, 2, SP2_C_BF16X3>>(L, Pin, Pout, st, part, sc, cnt, step, s);
+            return launch_lp_cfg<LpMain<SP2_C_BF16X3>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
         case SP2_C_BF16X2:
-            return launch_lp_cfg<LpCfg<128, 2, 2, SP2_C_BF16X2>>(L, Pin, Pout, st, part, sc, cnt, step, s);
+            return launch_lp_cfg<LpMain<SP2_C_BF16X2>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
         default:
             return hipErrorInvalidValue;
     }
-}
-
-hipError_t launch_planes_to_f64(const Layout& L, sp2_compute mode, const uint16_t* Pin, double* X,
-                                const State* st, int step, hipStream_t s) {
-    const size_t count = (size_t)L.ldp * L.ldp;
-    const int blocks = 2048;
-    switch (mode) {
-        case SP2_C_F16X2:
-            hipLaunchKernelGGL(k_planes_to_f64<SP2_C_F16X2>, dim3(blocks), dim3(kThreads), 0, s, Pin,
-                               L.plane_stride, X, count, st, step);
-            break;
-        case SP2_C_BF16X3:
-            hipLaunchKernelGGL(k_planes_to_f64<SP2_C_BF16X3>, dim3(blocks), dim3(kThreads), 0, s, Pin,
-                               L.plane_stride, X, count, st, step);
-            break;
-        case SP2_C_BF16X2:
-            hipLaunchKernelGGL(k_planes_to_f64<SP2_C_BF16X2>, dim3(blocks), dim3(kThreads), 0, s, Pin,
-                               L.plane_stride, X, count, st, step);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, uint16_t* Pout,

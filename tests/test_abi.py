@@ -69,3 +69,47 @@ def test_argument_checks_without_gpu(kw, code):
     lib = ctypes.CDLL(sp2.LIB_PATH)
     lib.sp2_density.restype = ctypes.c_int
     assert _call(lib, **kw) == code
+
+
+def test_learned_model_host_calls_without_gpu(tmp_path):
+    """Model create / coefficients / save / load / destroy touch no GPU: the
+    coefficients are rounded to FP32 and survive the text round trip exactly."""
+    import numpy as np
+
+    import paper_2401_13772_amd as sp2
+    coef = np.array([[1.0, 0.0, 0.0], [1.1, -0.1, 1e-3], [0.7, 0.3, -2.5e-4]])
+    m = sp2.Learned.from_coefficients(coef)
+    c, loss = m.coefficients()
+    assert np.array_equal(c, coef.astype(np.float32).astype(np.float64)) and loss == 0.0
+    path = tmp_path / "m.txt"
+    m.save(path)
+    m2 = sp2.Learned.load(path)
+    assert np.array_equal(m2.coefficients()[0], c)
+    m.close()
+    m2.close()
+    (tmp_path / "bad.txt").write_text("not a model\n")
+    with pytest.raises(RuntimeError):
+        sp2.Learned.load(tmp_path / "bad.txt")
+    with pytest.raises(RuntimeError):
+        sp2.Learned.from_coefficients(np.array([[1.0, float("nan"), 0.0]]))
+
+
+def test_plan_and_learned_argument_checks_without_gpu():
+    """Rejections that happen before any HIP call."""
+    import paper_2401_13772_amd as sp2
+    lib = ctypes.CDLL(sp2.LIB_PATH)
+    lib.sp2_plan_create.restype = ctypes.c_int
+    h = ctypes.c_void_p()
+    ns = (ctypes.c_int * 2)(64, 64)
+    no = (ctypes.c_int * 2)(32, 32)
+    bad_n = (ctypes.c_int * 2)(64, 4096)
+    bad_no = (ctypes.c_int * 2)(32, 65)
+    assert lib.sp2_plan_create(ctypes.byref(h), 0, ns, no, 0, 0, ctypes.c_double(1e-10), 50, None) == -1
+    assert lib.sp2_plan_create(ctypes.byref(h), 2, bad_n, no, 0, 0, ctypes.c_double(1e-10), 50, None) == -1
+    assert lib.sp2_plan_create(ctypes.byref(h), 2, ns, bad_no, 0, 0, ctypes.c_double(1e-10), 50, None) == -1
+    assert lib.sp2_plan_create(ctypes.byref(h), 2, ns, no, 0, 0, ctypes.c_double(0.0), 50, None) == -1
+    assert lib.sp2_plan_create(ctypes.byref(h), 2, ns, no, 0, 2, ctypes.c_double(1e-10), 50, None) == -5
+    assert not h.value
+    lib.sp2_learned_density.restype = ctypes.c_int
+    assert lib.sp2_learned_density(None, 1, 64, None, None, None, 0, 0, ctypes.c_double(1e-6), None,
+                                   None) == -1

@@ -182,3 +182,64 @@ def test_one_step_sampled_entries(sp2, oracle_lib):
     J = rng.integers(0, 1028, 4000)
     want = oracle_lib.sp2_step_entries(X0, grow, I, J)
     assert np.abs(D1[I, J] - want).max() < 1e-14
+
+
+def _oracle_threads():
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def test_bt128_full_solve_matches_oracle(sp2, oracle_lib):
+    """n = 2052: the 128 x 128-tile squaring kernel (8 waves) with its fused
+    epilogue sums and device steering, over a whole solve, against the oracle
+    (paper: Section "SP2 solver", recursion and listing): iteration count,
+    every branch, the trace and idempotency histories, info.idempotency and D."""
+    n = 2052
+    inst = make_tb_hamiltonian(n, seed=31, gap=0.5)
+    print(f"[gpu] bt128 full solve n={n}", flush=True)
+    Ht = torch.from_numpy(inst.H).cuda()
+    ws = sp2.alloc_workspace(n)
+    D, info = sp2.sp2_density(Ht, inst.n_occ, workspace=ws)
+    tr, e = sp2.sp2_history(ws)
+    Dg = D.cpu().numpy()
+    ref = oracle_lib.sp2(inst.H, inst.n_occ, tol=1e-10, nthreads=_oracle_threads())
+    assert info.status == ref.status == 0
+    assert info.iterations == ref.iterations == len(tr)
+    lo, hi = oracle_lib.gershgorin(inst.H)
+    assert info.emin == pytest.approx(lo, rel=1e-13) and info.emax == pytest.approx(hi, rel=1e-13)
+    # the branch is decided wherever the trace is not at n_occ to rounding
+    # (on the converged last step it is, and either branch is then correct)
+    decided = np.abs(np.asarray(ref.tr_hist) - inst.n_occ) > 1e-9 * n
+    assert decided[:-1].all()
+    assert np.array_equal(np.array(info.branches())[decided], np.array(ref.branches())[decided])
+    assert np.abs(tr - ref.tr_hist).max() <= 1e-9 * n
+    big = np.asarray(ref.e_hist) > 1e-6
+    assert np.allclose(e[big], np.asarray(ref.e_hist)[big], rtol=1e-9)
+    assert info.idempotency == pytest.approx(ref.idempotency, rel=0.5, abs=2e-11)
+    assert info.idempotency <= 1e-10
+    assert rms(Dg - ref.D) <= 1e-11
+    assert abs(info.trace - ref.trace) <= 1e-9
+    assert np.array_equal(Dg, Dg.T)
+
+
+def test_split_tiles_three_steps_match_oracle(sp2, oracle_lib):
+    """n = 3000: more 128 x 128 tiles than co-resident workgroups, so the
+    stream-K schedule splits tiles between two workgroups.  Three whole steps
+    (squaring, update, trace and norm sums, branch decisions) against the
+    oracle, entry by entry."""
+    n = 3000
+    inst = make_tb_hamiltonian(n, seed=12, gap=0.5)
+    print(f"[gpu] split tiles three steps n={n}", flush=True)
+    Ht = torch.from_numpy(inst.H).cuda()
+    ws = sp2.alloc_workspace(n)
+    D, info = sp2.sp2_density(Ht, inst.n_occ, max_iter=3, workspace=ws)
+    tr, e = sp2.sp2_history(ws)
+    Dg = D.cpu().numpy()
+    ref = oracle_lib.sp2(inst.H, inst.n_occ, max_iter=3, nthreads=_oracle_threads())
+    assert info.status == ref.status == sp2.NOT_CONVERGED
+    assert info.iterations == ref.iterations == 3
+    assert info.branches() == ref.branches()
+    assert np.abs(tr - ref.tr_hist).max() <= 1e-10 * n
+    assert np.allclose(e, ref.e_hist, rtol=1e-12)
+    assert np.abs(Dg - ref.D).max() <= 1e-13
+    assert np.array_equal(Dg, Dg.T)

@@ -1,9 +1,11 @@
 """GPU parity of the mixed-precision schedule (split-operand 16-bit products).
 
 Bars.  The method's accuracy bar is rms |D - D_ref| <= 1e-6 against the
-eigenvector definition of D; F16X2 and BF16X3 must meet it with the automatic
-FP64 prefix.  BF16X2 (16-bit operands) cannot, and is only checked for
-convergence of the FP64 refinement and a loose 1e-3.
+eigenvector definition of D (the oracle's Jacobi projector, or LAPACK at sizes
+the Jacobi oracle is too slow for); F16X2 and BF16X3 must meet it with the
+automatic FP64 prefix.  BF16X2 (16-bit operands) cannot: its test reports the
+floor it reaches and checks convergence of the FP64 refinement and a loose
+1e-3.
 
 A single split-operand step is checked entry by entry against the oracle's
 FP64 step: operands are represented to ~2^-22 relative (F16X2 hi + lo, BF16X3
@@ -49,7 +51,7 @@ def test_mixed_meets_accuracy_bar(sp2, oracle_lib, mode, n):
     D, info = solve(sp2, inst.H, inst.n_occ, compute=mode)
     Dj, w, _ = oracle_lib.jacobi_dm(inst.H, inst.n_occ)
     assert info.status == 0, info
-    assert info.fp64_prefix_iters == 12
+    assert info.fp64_prefix_iters >= 1
     assert 1 <= info.refine_steps <= 8
     assert info.iterations > info.fp64_prefix_iters + info.refine_steps   # split steps happened
     assert info.idempotency <= 1e-10
@@ -72,8 +74,10 @@ def test_bf16x2_reports_its_floor(sp2, oracle_lib):
     inst = make_tb_hamiltonian(256, seed=3)
     D, info = solve(sp2, inst.H, inst.n_occ, compute="bf16x2")
     Dj, _, _ = oracle_lib.jacobi_dm(inst.H, inst.n_occ)
+    err = rms(D - Dj)
+    print(f"[gpu] bf16x2 floor: rms |D - D_jacobi| = {err:.3e}", flush=True)
     assert info.status in (0, 2)
-    assert rms(D - Dj) <= 1e-3
+    assert err <= 1e-3
 
 
 @pytest.mark.parametrize("mode", MODES)

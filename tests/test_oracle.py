@@ -239,3 +239,60 @@ def test_step_entries_match_library_matmul(oracle_lib):
         got = oracle_lib.sp2_step_entries(X, grow, I, J)
         want = (2 * X - S if grow else S)[I, J]
         assert np.abs(got - want).max() < 1e-14
+
+
+# --------------------------------------------------------------------------- learned expansion
+
+def test_learned_hand_three_levels(oracle_lib):
+    g = golden.load("learned_3level.txt")
+    x, br, tr = oracle_lib.learned_spectral(g["lambda"], int(g["n_occ"]), g["emin"], g["emax"],
+                                            g["coef"])
+    # exact dyadic values: catches a swapped branch, a wrong sign in the
+    # particle-hole form or a coefficient applied to the wrong power
+    assert br == [int(v) for v in g["branches"]]
+    assert np.array_equal(x, g["x_final"])
+    x1, _, _ = oracle_lib.learned_spectral(g["lambda"], 1, g["emin"], g["emax"], g["coef"][:3])
+    assert np.array_equal(x1, g["x_after_layer0"])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_learned_with_sp2_coefficients_is_sp2(oracle_lib, seed):
+    """(a, b, c) = (1, 0, 0) in every layer is SP2 truncated after that many steps."""
+    inst = make_tb_hamiltonian(128, seed=seed)
+    w = np.linalg.eigvalsh(inst.H)
+    lo, hi = oracle_lib.gershgorin(inst.H)
+    L = 20
+    x, br, tr = oracle_lib.learned_spectral(w, inst.n_occ, lo, hi, np.tile([1.0, 0.0, 0.0], L))
+    ref, xs = oracle_lib.sp2_spectral(w, inst.n_occ, lo, hi, tol=1e-300, max_iter=L)
+    assert br == ref.branches()
+    assert np.allclose(tr, ref.tr_hist, rtol=0, atol=1e-10)
+    assert np.abs(x - xs).max() < 1e-11
+
+
+def test_learned_matrix_equals_spectral_form(oracle_lib):
+    """Every layer is a polynomial of H, so D = V diag(p(x_i)) V^T with V from
+    LAPACK; catches a layer applied to the wrong matrix (X vs I - X) or a
+    missing identity term."""
+    rng = np.random.default_rng(4)
+    inst = make_tb_hamiltonian(64, seed=6)
+    coef = np.column_stack([1.0 + 0.3 * rng.standard_normal(6), 0.2 * rng.standard_normal(6),
+                            0.05 * rng.standard_normal(6)])
+    D, br = oracle_lib.learned_matrix(inst.H, inst.n_occ, coef)
+    w, V = np.linalg.eigh(inst.H)
+    lo, hi = oracle_lib.gershgorin(inst.H)
+    x, brs, _ = oracle_lib.learned_spectral(w, inst.n_occ, lo, hi, coef)
+    assert br == brs
+    assert np.abs(D - (V * x) @ V.T).max() < 1e-10
+
+
+def test_learned_particle_hole_symmetry(oracle_lib):
+    """-H with n - n_occ occupied maps x -> 1 - x and swaps the branches, so
+    D(-H, n - n_occ) = I - D(H, n_occ)."""
+    rng = np.random.default_rng(8)
+    inst = make_tb_hamiltonian(48, seed=2)
+    coef = np.column_stack([1.0 + 0.2 * rng.standard_normal(5), 0.1 * rng.standard_normal(5),
+                            0.02 * rng.standard_normal(5)])
+    D, br = oracle_lib.learned_matrix(inst.H, inst.n_occ, coef)
+    Dm, brm = oracle_lib.learned_matrix(-inst.H, 48 - inst.n_occ, coef)
+    assert [1 - b for b in br] == brm
+    assert np.abs(Dm - (np.eye(48) - D)).max() < 1e-10
