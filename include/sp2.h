@@ -63,7 +63,9 @@ typedef enum {
                          then FP64 refinement */
     SP2_C_BF16X3 = 3, /* mixed, as above with three BF16 planes (6 products) */
     SP2_C_BF16X2 = 4, /* mixed, as above with two BF16 planes (3 products) */
-    SP2_C_FP8 = 5     /* reserved */
+    SP2_C_FP8 = 5     /* mixed, as F16X2 with two OCP e4m3 planes x ~ 2^-8 q0 +
+                         2^-12 q1 (fixed power-of-two scales: SP2 iterates
+                         satisfy |x| <= 1), 3 products on the FP8 MFMA */
 } sp2_compute;
 
 typedef enum {
@@ -202,11 +204,15 @@ int sp2_plan_destroy(sp2_plan* plan);
  * sp2_learned_save / sp2_learned_load: text file (hex floats, exact).
  * sp2_learned_density: batch matrices of one size n (device pointers,
  *   row-major, leading dimension n, storage dtype), occupations n_occ[b]:
- *   the trained layers, then one SP2 step whose input must satisfy
- *   ||X^2 - X||_F <= idem_fallback and |tr - n_occ| <= idem_fallback; D gets
- *   the output of that step.  Matrices that fail are solved again from H by
- *   plain FP64 SP2 (tol 1e-10) and reported as SP2_E_FALLBACK, with
- *   info.refine_steps = the learned steps taken before the rejection.
+ *   the trained layers, then an SP2 check step on their output X_L.  If
+ *   ||X_L^2 - X_L||_F <= idem_fallback and the trace error is within
+ *   idem_fallback, D is the check step's output (status SP2_OK).  Else, if
+ *   ||X_L^2 - X_L||_F <= 0.25 (every eigenvalue within (-0.21, 1.21)), plain
+ *   trace-steered SP2 steps continue on the device with sp2_density's stop
+ *   rule (tol 1e-10), up to 60 of them.  Else the matrix is solved again from H
+ *   by plain FP64 SP2 and reported as SP2_E_FALLBACK.  info.fp64_prefix_iters
+ *   = the learned layers applied, info.refine_steps = the plain SP2 steps
+ *   after them (or of the solve from H), info.iterations = all squarings.
  *   compute: SP2_C_F64 (others SP2_E_UNSUPPORTED).  The model keeps an
  *   inference plan for the last (batch, n, n_occ, dtype, bar) and a
  *   workspace for the fallback solves; calls on one model must not overlap.
@@ -224,6 +230,30 @@ int sp2_learned_density(sp2_learned* model, int batch, int n, const void* const*
                         const int* n_occ, sp2_dtype dtype, sp2_compute compute, double idem_fallback,
                         void* hip_stream, sp2_info* infos);
 int sp2_learned_destroy(sp2_learned* model);
+
+/*
+ * Chebyshev expansion of the Fermi operator (Section "Chebyshev polynomial
+ * expansion"): D = sum_{t < k m} c_t T_t(Hs) with Hs = ((H + H^T)/2 - a I)/b,
+ * a, b the centre and half width of the Gershgorin interval, and c_t the
+ * Chebyshev coefficients (Chebyshev-Gauss rule, 4 k m nodes) of the
+ * Fermi-Dirac occupation 1/(1 + exp(beta (e - mu))) (mu, beta in the units of
+ * H).  For finite temperature or a vanishing gap, where SP2 is not suited.
+ * Evaluated in the section's Paterson-Stockmeyer form sum_j T_k^j S_j,
+ * S_j = sum_{i<k} d_{i,j} T_i: T_2..T_k level by level (each level one
+ * grouped launch), then m - 1 Horner products; k + m - 2 matrix products in
+ * all.  1 <= k <= 64, 1 <= m <= k + 4, n <= 32768.
+ *   H, D        device pointers, n x n, row-major, leading dimension ld,
+ *               storage dtype; D may be uninitialised.
+ *   workspace   at least sp2_cheb_workspace_size(n, k) bytes (k + 2 padded
+ *               FP64 matrices and work lists), SP2_WORKSPACE_ALIGN aligned.
+ * One host synchronisation after the bounds (their values set the
+ * coefficients), one at the end.  info: status, iterations = matrix
+ * products, trace = tr D, emin/emax.  Returns SP2_OK or a negative status
+ * (D untouched).
+ */
+size_t sp2_cheb_workspace_size(int n, int k);
+int sp2_cheb_density(const void* H, void* D, int n, int ld, sp2_dtype dtype, double mu, double beta, int k,
+                     int m, void* workspace, size_t workspace_bytes, void* hip_stream, sp2_info* info);
 
 /*
  * Copy the per-step history of the last sp2_density call that used

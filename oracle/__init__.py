@@ -64,6 +64,10 @@ def _load():
         lib.oracle_sp2_step_entries.argtypes = [d, ctypes.c_int, ctypes.c_int, i, i,
                                                 ctypes.c_int, d]
         lib.oracle_sp2_step_entries.restype = None
+        lib.oracle_cheb_coeffs.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, d]
+        lib.oracle_cheb_density.argtypes = [d, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int, ctypes.c_int, d, d, d]
+        lib.oracle_cheb_ps_split.argtypes = [d, ctypes.c_int, ctypes.c_int, d]
         u64 = ctypes.POINTER(ctypes.c_uint64)
         lib.oracle_learned_spectral.argtypes = [d, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                                 ctypes.c_double, d, ctypes.c_int, d, u64, d]
@@ -231,3 +235,42 @@ def learned_matrix(H, n_occ, coef, nthreads=1):
         raise ValueError(f"oracle_learned_matrix status {st}")
     m = int(mask[0]) | (int(mask[1]) << 64)
     return D, [(m >> k) & 1 for k in range(L)]
+
+
+def cheb_coeffs(L, beta_scaled, mu_scaled, q=None):
+    """c_0..c_L of 1/(1 + exp(beta_scaled (x - mu_scaled))) on [-1, 1] (Chebyshev-Gauss
+    rule, q nodes; paper: Section "Chebyshev polynomial expansion", first equation)."""
+    q = 4 * (L + 1) if q is None else q
+    c = np.zeros(L + 1)
+    st = _load().oracle_cheb_coeffs(int(L), float(beta_scaled), float(mu_scaled), int(q), _dp(c))
+    if st != OK:
+        raise ValueError(f"oracle_cheb_coeffs status {st}")
+    return c
+
+
+def cheb_density(H, L, beta, mu, q=None, nthreads=1):
+    """sum_{n<=L} c_n T_n((H - a)/b) by the serial recursion T_{n+1} = 2 H T_n - T_{n-1}
+    (paper: Section "Chebyshev polynomial expansion").  Returns (D, c, (a, b))."""
+    H = _f64(H)
+    q = 4 * (L + 1) if q is None else q
+    D = np.empty_like(H)
+    c = np.zeros(L + 1)
+    ab = np.zeros(2)
+    st = _load().oracle_cheb_density(_dp(H), H.shape[0], int(L), float(beta), float(mu), int(q),
+                                     int(nthreads), _dp(D), _dp(c), _dp(ab))
+    if st != OK:
+        raise ValueError(f"oracle_cheb_density status {st}")
+    return D, c, (ab[0], ab[1])
+
+
+def cheb_ps_split(c, k, m):
+    """d[j, i] of sum_n c_n T_n = sum_j T_k^j sum_{i<k} d[j, i] T_i (Paterson-Stockmeyer
+    form of the paper's ansatz equation); len(c) must be k m."""
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+    if c.size != k * m:
+        raise ValueError("len(c) must be k m")
+    d = np.zeros(k * m)
+    st = _load().oracle_cheb_ps_split(_dp(c), int(k), int(m), _dp(d))
+    if st != OK:
+        raise ValueError(f"oracle_cheb_ps_split status {st}")
+    return d.reshape(m, k)

@@ -28,6 +28,14 @@
  *                        (a polynomial of H acts on each eigenvalue alone).
  *   oracle_sp2_step_entries  single entries of one SP2 step, for sampled
  *                        checks at sizes where the full loop is too slow.
+ *   oracle_cheb_coeffs, oracle_cheb_density, oracle_cheb_ps_split
+ *                        the Chebyshev expansion of the Fermi operator of
+ *                        Section "Chebyshev polynomial expansion": the
+ *                        coefficients c_n of the Fermi-Dirac function on the
+ *                        spectrum scaled into [-1, 1], the serial recursion
+ *                        T_{n+1} = 2 H T_n - T_{n-1} summed on the matrix,
+ *                        and the coefficients d_{i,j} of the
+ *                        Paterson-Stockmeyer form sum_j T_k^j S_j.
  *   oracle_learned_spectral, oracle_learned_matrix
  *                        a learned recursive expansion: a composition of
  *                        trained quadratic maps of the matrix (Section "GPU
@@ -268,6 +276,24 @@ static void square(const double* X, double* S, int n, int nthreads)
             double xik = X[(long)i * n + k];
             const double* Xk = X + (long)k * n;
             for (int j = 0; j < n; ++j) Si[j] += xik * Xk[j];
+        }
+    }
+}
+
+/* S = A B (n x n, row-major), summing over k in increasing order. */
+static void square_pair(const double* A, const double* B, double* S, int n, int nthreads)
+{
+    (void)nthreads;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+    for (int i = 0; i < n; ++i) {
+        double* Si = S + (long)i * n;
+        for (int j = 0; j < n; ++j) Si[j] = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double aik = A[(long)i * n + k];
+            const double* Bk = B + (long)k * n;
+            for (int j = 0; j < n; ++j) Si[j] += aik * Bk[j];
         }
     }
 }
@@ -516,5 +542,129 @@ int oracle_learned_matrix(const double* H, int n, int n_occ, const double* coef,
     }
     memcpy(D, X, sizeof(double) * (size_t)nn);
     free(X); free(Y); free(S);
+    return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Chebyshev expansion of the Fermi operator                               */
+/* ---------------------------------------------------------------------- */
+
+/* Fermi-Dirac occupation 1 / (1 + exp(t)), evaluated without overflow. */
+static double fermi(double t)
+{
+    if (t > 0.0) { double e = exp(-t); return e / (1.0 + e); }
+    return 1.0 / (1.0 + exp(t));
+}
+
+/*
+ * c_0..c_L of f(x) = 1/(1 + exp(bs (x - ms))) on [-1, 1] (bs, ms: the inverse
+ * temperature and chemical potential in the scaled variable), by the
+ * Chebyshev-Gauss rule with q nodes:
+ *   c_n = (2 - [n == 0]) / q * sum_{j<q} f(cos t_j) cos(n t_j),
+ *   t_j = pi (j + 1/2) / q.
+ */
+int oracle_cheb_coeffs(int L, double bs, double ms, int q, double* c)
+{
+    if (L < 0 || q < L + 1 || !c) return ORACLE_INVALID;
+    const double pi = 3.14159265358979323846;
+    for (int n = 0; n <= L; ++n) {
+        double acc = 0.0;
+        for (int j = 0; j < q; ++j) {
+            double t = pi * (j + 0.5) / q;
+            acc += fermi(bs * (cos(t) - ms)) * cos(n * t);
+        }
+        c[n] = (n == 0 ? 1.0 : 2.0) * acc / q;
+    }
+    return ORACLE_OK;
+}
+
+/*
+ * D = sum_{n<=L} c_n T_n(Hs) with Hs = (H - a I)/b, a and b the centre and
+ * half width of the Gershgorin interval, by the serial recursion
+ * T_{n+1} = 2 Hs T_n - T_{n-1} (triple-loop products).  mu and beta in the
+ * units of H; q nodes for the coefficients (q >= L + 1).  coef (may be NULL,
+ * length L + 1) receives c_n; bounds (may be NULL) a and b.
+ */
+int oracle_cheb_density(const double* H, int n, int L, double beta, double mu, int q, int nthreads,
+                        double* D, double* coef, double* bounds)
+{
+    if (n <= 0 || !H || !D || L < 0 || q < L + 1 || !(beta > 0.0)) return ORACLE_INVALID;
+    double emin, emax;
+    int st = oracle_gershgorin(H, n, &emin, &emax);
+    if (st != ORACLE_OK) return st;
+    if (!(emax > emin)) return ORACLE_DEGENERATE;
+    const double a = (emax + emin) / 2.0, b = (emax - emin) / 2.0;
+    if (bounds) { bounds[0] = a; bounds[1] = b; }
+    long nn = (long)n * n;
+    double* c = (double*)malloc(sizeof(double) * (size_t)(L + 1));
+    double* Hs = (double*)malloc(sizeof(double) * (size_t)nn);
+    double* Tm = (double*)malloc(sizeof(double) * (size_t)nn);   /* T_{k-1} */
+    double* T = (double*)malloc(sizeof(double) * (size_t)nn);    /* T_k */
+    double* Tn = (double*)malloc(sizeof(double) * (size_t)nn);   /* T_{k+1} */
+    if (!c || !Hs || !Tm || !T || !Tn) {
+        free(c); free(Hs); free(Tm); free(T); free(Tn);
+        return ORACLE_NOMEM;
+    }
+    oracle_cheb_coeffs(L, beta * b, (mu - a) / b, q, c);
+    if (coef) memcpy(coef, c, sizeof(double) * (size_t)(L + 1));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            long p = (long)i * n + j;
+            double hs = (H[p] + H[(long)j * n + i]) / 2.0;
+            Hs[p] = ((i == j ? hs - a : hs)) / b;
+            Tm[p] = (i == j) ? 1.0 : 0.0;           /* T_0 */
+            T[p] = Hs[p];                           /* T_1 */
+            D[p] = c[0] * Tm[p];
+        }
+    if (L >= 1)
+        for (long p = 0; p < nn; ++p) D[p] += c[1] * T[p];
+    for (int k = 1; k < L; ++k) {
+        square_pair(Hs, T, Tn, n, nthreads);
+        for (long p = 0; p < nn; ++p) {
+            Tn[p] = 2.0 * Tn[p] - Tm[p];
+            D[p] += c[k + 1] * Tn[p];
+        }
+        double* t = Tm; Tm = T; T = Tn; Tn = t;
+    }
+    free(c); free(Hs); free(Tm); free(T); free(Tn);
+    return ORACLE_OK;
+}
+
+/*
+ * The Paterson-Stockmeyer form: given c_0..c_{k m - 1}, the d_{i,j}
+ * (i < k, j < m; d[j * k + i]) with sum_n c_n T_n = sum_j T_k^j S_j,
+ * S_j = sum_{i<k} d_{i,j} T_i.  By repeated division by T_k in the
+ * Chebyshev basis: for the highest remaining degree t >= k,
+ * T_t = 2 T_k T_{t-k} - T_{|2k - t|} (T_k T_0 = T_k for t = k) moves the
+ * coefficient of T_t into the quotient; what remains below k is S_j.
+ */
+int oracle_cheb_ps_split(const double* c, int k, int m, double* d)
+{
+    if (!c || !d || k < 1 || m < 1) return ORACLE_INVALID;
+    int N = k * m;
+    double* a = (double*)malloc(sizeof(double) * (size_t)N);
+    double* qt = (double*)malloc(sizeof(double) * (size_t)N);
+    if (!a || !qt) { free(a); free(qt); return ORACLE_NOMEM; }
+    memcpy(a, c, sizeof(double) * (size_t)N);
+    int deg = N - 1;
+    for (int j = 0; j < m; ++j) {
+        for (int t = 0; t < N; ++t) qt[t] = 0.0;
+        for (int t = deg; t >= k; --t) {
+            double v = a[t];
+            a[t] = 0.0;
+            if (t == k) {
+                qt[0] += v;
+            } else {
+                qt[t - k] += 2.0 * v;
+                int r = 2 * k - t;
+                if (r < 0) r = -r;
+                a[r] -= v;
+            }
+        }
+        for (int i = 0; i < k; ++i) d[j * k + i] = (i <= deg) ? a[i] : 0.0;
+        deg -= k;
+        for (int t = 0; t < N; ++t) a[t] = qt[t];
+    }
+    free(a); free(qt);
     return ORACLE_OK;
 }

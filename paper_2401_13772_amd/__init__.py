@@ -64,6 +64,12 @@ _lib.sp2_plan_config.argtypes = [_vp]
 _lib.sp2_plan_destroy.restype = ctypes.c_int
 _lib.sp2_plan_destroy.argtypes = [_vp]
 PLAN_MAX_N = 2048
+_lib.sp2_cheb_workspace_size.restype = ctypes.c_size_t
+_lib.sp2_cheb_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int]
+_lib.sp2_cheb_density.restype = ctypes.c_int
+_lib.sp2_cheb_density.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp,
+                                  ctypes.POINTER(sp2_info)]
 _lib.sp2_learned_create.restype = ctypes.c_int
 _lib.sp2_learned_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
 _lib.sp2_learned_fit.restype = ctypes.c_int
@@ -206,6 +212,37 @@ def sp2_history(workspace, count: int = MAX_ITER, stream=None):
     if m < 0:
         raise RuntimeError(f"sp2_history failed: {sp2_status_str(m)}")
     return np.array(tr[:m]), np.array(e[:m])
+
+
+def sp2_cheb_workspace_size(n: int, k: int) -> int:
+    return int(_lib.sp2_cheb_workspace_size(int(n), int(k)))
+
+
+def sp2_cheb_density(H, mu: float, beta: float, k: int, m: int, D=None, workspace=None, stream=None):
+    """Chebyshev expansion of the Fermi operator (sp2_cheb_density): k m terms in
+    Paterson-Stockmeyer form.  H: (n, n) device tensor, row-major (leading
+    dimension H.stride(0)).  Returns (D, Info)."""
+    import torch
+    if H.dim() != 2 or H.stride(1) != 1:
+        raise ValueError("H must be a 2-D row-major device tensor")
+    n = H.shape[0]
+    ld = H.stride(0)
+    if D is None:
+        D = torch.empty((n, ld), dtype=H.dtype, device=H.device)[:, :n]
+    if D.dtype != H.dtype or D.stride(0) != ld or D.stride(1) != 1:
+        raise ValueError("D must have H's dtype and leading dimension, row-major")
+    nbytes = sp2_cheb_workspace_size(n, k)
+    if nbytes == 0:
+        raise ValueError("invalid size or k")
+    if workspace is None:
+        ws = torch.empty(nbytes + WORKSPACE_ALIGN, dtype=torch.uint8, device=H.device)
+        off = (-ws.data_ptr()) % WORKSPACE_ALIGN
+        workspace = ws[off:off + nbytes]
+    info = sp2_info()
+    _lib.sp2_cheb_density(_vp(H.data_ptr()), _vp(D.data_ptr()), int(n), int(ld), _dtype_code(H.dtype),
+                          float(mu), float(beta), int(k), int(m), _vp(workspace.data_ptr()),
+                          int(workspace.numel()), _stream_handle(stream), ctypes.byref(info))
+    return D, _info(info)
 
 
 class Plan:
@@ -396,5 +433,5 @@ def exported_symbols():
     return ["sp2_version", "sp2_status_str", "sp2_workspace_size", "sp2_density", "sp2_history", "sp2_plan_create", "sp2_plan_run",
             "sp2_plan_config", "sp2_plan_destroy", "sp2_learned_create", "sp2_learned_fit",
             "sp2_learned_coefficients", "sp2_learned_save", "sp2_learned_load", "sp2_learned_density",
-            "sp2_learned_destroy",
+            "sp2_learned_destroy", "sp2_cheb_workspace_size", "sp2_cheb_density",
             "sp2_profile_enable", "sp2_profile_read", "sp2_profile_read_split"]

@@ -7,13 +7,14 @@
 //     working buffer,
 //   * the final copy of the converged iterate into the caller's D.
 //
-// Every kernel streams H or X once through 64x64 tiles: rows are read with
-// consecutive lanes on consecutive columns, and the transposed partner tile
-// needed for (H + H^T)/2 goes through LDS so that both reads stay coalesced.
-// Reductions are deterministic: fixed per-thread order, fixed wave/block
-// order, and a last-arriving block that sums the per-block partials in index
-// order.
-#include "sp2_device.h"
+// The bounds and X_0 kernels each read H once: a block takes a pair of 64x64
+// tiles (I, J) and (J, I), both read row-wise (consecutive lanes on
+// consecutive columns) into LDS, where the transposed element that
+// (H + H^T)/2 needs is at hand; X_0's mirrored tile is written row-wise from
+// the transposed LDS tile.  Reductions are deterministic: fixed per-thread
+// order, fixed wave/block order, and per-block partials added in block order
+// by a final kernel.
+#include "bounds_core.h"
 
 namespace sp2 {
 
@@ -27,58 +28,27 @@ __global__ void k_reset(State* st, int n, int n_occ, double tol, int max_iter, i
 template <typename T>
 __device__ inline double ld_h(const T* H, size_t idx) { return (double)H[idx]; }
 
-// Row partial radii: block (rb, split) covers rows [64 rb, 64 rb + 64) and the
-// column tiles [8 split, 8 split + 8).  rowpart[split * ldp + i] receives
-// sum_{j in those columns, j != i} |Hs_ij|.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bounds_partial(const T* __restrict__ H, int n, int ld,
-                                                             double* __restrict__ rowpart, int ldp,
-                                                             State* st) {
+__global__ __launch_bounds__(kThreads) void k_bounds_pair(const T* __restrict__ H, int n, int ld,
+                                                          double* __restrict__ rowpart, int ldp,
+                                                          State* st) {
     __shared__ double sA[kBndTile][kBndTile + 1];
     __shared__ double sB[kBndTile][kBndTile + 1];
-    const int rb = blockIdx.x, split = blockIdx.y;
-    const int tid = threadIdx.x;
-    const int r = tid >> 2, sub = tid & 3;
-    const int gi = rb * kBndTile + r;
-    const int ncb = (n + kBndTile - 1) / kBndTile;
-    const int per = kBndColsPerBlock / kBndTile;
-    const int cb0 = split * per;
-    const int cb1 = min(ncb, cb0 + per);
-    double acc = 0.0;
+    int I, J;
+    tri_tile(blockIdx.x, I, J);
     int bad = 0;
-    for (int cb = cb0; cb < cb1; ++cb) {
-        for (int e = tid; e < kBndTile * kBndTile; e += kThreads) {
-            const int rr = e >> 6, cc = e & 63;
-            const int ra = rb * kBndTile + rr, ca = cb * kBndTile + cc;
-            const int rbb = cb * kBndTile + rr, cbb = rb * kBndTile + cc;
-            sA[rr][cc] = (ra < n && ca < n) ? ld_h(H, (size_t)ra * ld + ca) : 0.0;
-            sB[rr][cc] = (rbb < n && cbb < n) ? ld_h(H, (size_t)rbb * ld + cbb) : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int j = 0; j < 16; ++j) {
-            const int c = sub * 16 + j;
-            const int gj = cb * kBndTile + c;
-            const double a = sA[r][c];
-            const double b = sB[c][r];
-            bad |= !isfinite(a);
-            const double hs = (a + b) / 2.0;
-            if (gj != gi && gj < n && gi < n) acc += fabs(hs);
-        }
-        __syncthreads();
-    }
-    // the four threads of a row are adjacent lanes: combine in a fixed pattern
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    if (sub == 0 && gi < n) rowpart[(size_t)split * ldp + gi] = acc;
+    load_pair(H, n, ld, I, J, sA, sB, bad);
+    __syncthreads();
+    pair_row_partials(n, I, J, sA, sB, rowpart, ldp);
     if (bad) atomicOr(&st->bad, 1);
 }
 
-// Per-row disc ends, block min/max, and the last block's global min/max.
+// Per-row disc ends (R_i = the column-tile partials added in tile order),
+// block min/max, and the last block's global min/max.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bounds_final(const T* __restrict__ H, int n, int ld,
                                                            const double* __restrict__ rowpart,
-                                                           int ldp, int nsplit,
+                                                           int ldp, int nb,
                                                            double* __restrict__ bpart, State* st) {
     __shared__ double red[2][4];
     __shared__ int last_flag;
@@ -86,8 +56,8 @@ __global__ __launch_bounds__(kThreads) void k_bounds_final(const T* __restrict__
     double lo = INFINITY, hi = -INFINITY;
     if (i < n) {
         double R = 0.0;
-        for (int s = 0; s < nsplit; ++s) R += rowpart[(size_t)s * ldp + i];
-        const double c = ld_h(H, (size_t)i * ld + i);
+        for (int K = 0; K < nb; ++K) R += rowpart[(size_t)K * ldp + i];
+        const double c = (double)H[(size_t)i * ld + i];
         lo = c - R;
         hi = c + R;
     }
@@ -125,56 +95,35 @@ __global__ __launch_bounds__(kThreads) void k_bounds_final(const T* __restrict__
     }
 }
 
-// X_0 tile (bi, bj) of the padded ldp x ldp FP64 buffer; zero outside n x n.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_init(const T* __restrict__ H, int n, int ld, int ldp,
-                                                   double* __restrict__ X0, double* __restrict__ part,
-                                                   State* st) {
+__global__ __launch_bounds__(kThreads) void k_init_pair(const T* __restrict__ H, int n, int ld, int ldp,
+                                                        double* __restrict__ X0, double* __restrict__ part,
+                                                        const State* st) {
+    __shared__ double sA[kBndTile][kBndTile + 1];
     __shared__ double sB[kBndTile][kBndTile + 1];
     __shared__ double red[4];
-    __shared__ int last_flag;
-    const int bi = blockIdx.y, bj = blockIdx.x;
-    const int nb = gridDim.x;
-    const int tid = threadIdx.x;
-    const double emin = st->emin, emax = st->emax;
-    const double width = emax - emin;
-    for (int e = tid; e < kBndTile * kBndTile; e += kThreads) {
-        const int rr = e >> 6, cc = e & 63;
-        const int gr = bj * kBndTile + rr, gc = bi * kBndTile + cc;
-        sB[rr][cc] = (gr < n && gc < n) ? ld_h(H, (size_t)gr * ld + gc) : 0.0;
-    }
+    int I, J;
+    tri_tile(blockIdx.x, I, J);
+    const double emax = st->emax, width = st->emax - st->emin;
+    int bad = 0;
+    load_pair(H, n, ld, I, J, sA, sB, bad);
     __syncthreads();
-    double trp = 0.0, fro = 0.0;
-    for (int e = tid; e < kBndTile * kBndTile; e += kThreads) {
-        const int rr = e >> 6, cc = e & 63;
-        const int gi = bi * kBndTile + rr, gj = bj * kBndTile + cc;
-        double x = 0.0;
-        if (gi < n && gj < n) {
-            const double a = ld_h(H, (size_t)gi * ld + gj);
-            const double hs = (a + sB[cc][rr]) / 2.0;
-            const double num = (gi == gj) ? (emax - hs) : (0.0 - hs);
-            x = num / width;
-        }
-        X0[(size_t)gi * ldp + gj] = x;
-        fro += x * x;
-        if (gi == gj) trp += x;
-    }
-    trp = block_sum(trp, red);
-    fro = block_sum(fro, red);
-    if (tid == 0) {
-        part[2 * (bi * nb + bj) + 0] = trp;
-        part[2 * (bi * nb + bj) + 1] = fro;
-    }
-    if (!arrive_last(st, gridDim.x * gridDim.y, &last_flag)) return;
-    const int tiles = nb * nb;
+    pair_x0(n, ldp, I, J, emax, width, sA, sB, X0, red, part, blockIdx.x);
+}
+
+// tr X_0 and ||X_0||^2 from the pair partials in pair order (one block), and
+// the start of the loop.
+__global__ __launch_bounds__(kThreads) void k_init_final(const double* __restrict__ part, int npairs,
+                                                         State* st) {
+    __shared__ double red[4];
     double t = 0.0, f = 0.0;
-    for (int k = tid; k < tiles; k += kThreads) {
+    for (int k = threadIdx.x; k < npairs; k += kThreads) {
         t += part[2 * k + 0];
         f += part[2 * k + 1];
     }
     t = block_sum(t, red);
     f = block_sum(f, red);
-    if (tid == 0) state_after_init(st, t, f);
+    if (threadIdx.x == 0) state_after_init(st, t, f);
 }
 
 // D <- last iterate (converted to the storage type), or 0 / I for the special
@@ -185,14 +134,16 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void k_finalize(T* __restrict__ D, int n, int ld, int ldp,
                                                        const double* __restrict__ x0,
                                                        const double* __restrict__ x1,
-                                                       const uint16_t* __restrict__ p0,
-                                                       const uint16_t* __restrict__ p1,
+                                                       const void* __restrict__ p0,
+                                                       const void* __restrict__ p1,
                                                        size_t pstride, const State* st) {
+    constexpr int PM = MODE == SP2_C_F64 ? SP2_C_F16X2 : MODE;   // plane format (unused for FP64)
+    typedef typename Planes<PM>::Elem E;
     if (st->status < 0) return;
     const int special = st->special;
     const int odd = st->iterations & 1;
     const double* src = odd ? x1 : x0;
-    const uint16_t* psrc = odd ? p1 : p0;
+    const E* psrc = (const E*)(odd ? p1 : p0);
     const bool from_planes = (MODE != SP2_C_F64) && st->stale;
     const int i = blockIdx.x;
     for (int j = threadIdx.x; j < n; j += kThreads) {
@@ -200,7 +151,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(T* __restrict__ D, int n,
         const size_t idx = (size_t)i * ldp + j;
         if (special == 1) v = 0.0;
         else if (special == 2) v = (i == j) ? 1.0 : 0.0;
-        else if (from_planes) v = load_planes<MODE == SP2_C_F64 ? SP2_C_F16X2 : MODE>(psrc, pstride, idx);
+        else if (from_planes) v = load_planes<PM>(psrc, pstride, idx);
         else v = src[idx];
         D[(size_t)i * ld + j] = (T)v;
     }
@@ -217,20 +168,20 @@ hipError_t launch_reset(State* st, int n, int n_occ, double tol, int max_iter, i
 hipError_t launch_bounds(const void* H, sp2_dtype dt, int n, int ld, const Layout& L, State* st,
                          double* rowpart, double* part, hipStream_t s) {
     (void)part;
-    const int nrb = (n + kBndTile - 1) / kBndTile;
-    const int nsplit = (n + kBndColsPerBlock - 1) / kBndColsPerBlock;
+    const int nb = L.ldp / kBndTile;
+    const int npairs = nb * (nb + 1) / 2;
     const int nfb = (n + kThreads - 1) / kThreads;
-    double* bpart = rowpart + (size_t)nsplit * L.ldp;
+    double* bpart = rowpart + (size_t)nb * L.ldp;
     if (dt == SP2_F64) {
-        hipLaunchKernelGGL(k_bounds_partial<double>, dim3(nrb, nsplit), dim3(kThreads), 0, s,
-                           (const double*)H, n, ld, rowpart, L.ldp, st);
-        hipLaunchKernelGGL(k_bounds_final<double>, dim3(nfb), dim3(kThreads), 0, s,
-                           (const double*)H, n, ld, (const double*)rowpart, L.ldp, nsplit, bpart, st);
+        hipLaunchKernelGGL(k_bounds_pair<double>, dim3(npairs), dim3(kThreads), 0, s, (const double*)H, n, ld,
+                           rowpart, L.ldp, st);
+        hipLaunchKernelGGL(k_bounds_final<double>, dim3(nfb), dim3(kThreads), 0, s, (const double*)H, n, ld,
+                           (const double*)rowpart, L.ldp, nb, bpart, st);
     } else {
-        hipLaunchKernelGGL(k_bounds_partial<float>, dim3(nrb, nsplit), dim3(kThreads), 0, s,
-                           (const float*)H, n, ld, rowpart, L.ldp, st);
-        hipLaunchKernelGGL(k_bounds_final<float>, dim3(nfb), dim3(kThreads), 0, s,
-                           (const float*)H, n, ld, (const double*)rowpart, L.ldp, nsplit, bpart, st);
+        hipLaunchKernelGGL(k_bounds_pair<float>, dim3(npairs), dim3(kThreads), 0, s, (const float*)H, n, ld,
+                           rowpart, L.ldp, st);
+        hipLaunchKernelGGL(k_bounds_final<float>, dim3(nfb), dim3(kThreads), 0, s, (const float*)H, n, ld,
+                           (const double*)rowpart, L.ldp, nb, bpart, st);
     }
     return hipGetLastError();
 }
@@ -238,18 +189,20 @@ hipError_t launch_bounds(const void* H, sp2_dtype dt, int n, int ld, const Layou
 hipError_t launch_init(const void* H, sp2_dtype dt, int n, int ld, const Layout& L, State* st,
                        double* x0, double* part, hipStream_t s) {
     const int nb = L.ldp / kBndTile;
+    const int npairs = nb * (nb + 1) / 2;
     if (dt == SP2_F64)
-        hipLaunchKernelGGL(k_init<double>, dim3(nb, nb), dim3(kThreads), 0, s, (const double*)H, n,
-                           ld, L.ldp, x0, part, st);
-    else
-        hipLaunchKernelGGL(k_init<float>, dim3(nb, nb), dim3(kThreads), 0, s, (const float*)H, n, ld,
+        hipLaunchKernelGGL(k_init_pair<double>, dim3(npairs), dim3(kThreads), 0, s, (const double*)H, n, ld,
                            L.ldp, x0, part, st);
+    else
+        hipLaunchKernelGGL(k_init_pair<float>, dim3(npairs), dim3(kThreads), 0, s, (const float*)H, n, ld,
+                           L.ldp, x0, part, st);
+    hipLaunchKernelGGL(k_init_final, dim3(1), dim3(kThreads), 0, s, (const double*)part, npairs, st);
     return hipGetLastError();
 }
 
 template <typename T>
 static void finalize_t(T* D, int n, int ld, const Layout& L, sp2_compute mode, const State* st,
-                       const double* x0, const double* x1, const uint16_t* p0, const uint16_t* p1,
+                       const double* x0, const double* x1, const void* p0, const void* p1,
                        hipStream_t s) {
     switch (mode) {
         case SP2_C_F16X2:
@@ -264,6 +217,10 @@ static void finalize_t(T* D, int n, int ld, const Layout& L, sp2_compute mode, c
             hipLaunchKernelGGL((k_finalize<T, SP2_C_BF16X2>), dim3(n), dim3(kThreads), 0, s, D, n, ld,
                                L.ldp, x0, x1, p0, p1, L.plane_stride, st);
             break;
+        case SP2_C_FP8:
+            hipLaunchKernelGGL((k_finalize<T, SP2_C_FP8>), dim3(n), dim3(kThreads), 0, s, D, n, ld,
+                               L.ldp, x0, x1, p0, p1, L.plane_stride, st);
+            break;
         default:
             hipLaunchKernelGGL((k_finalize<T, SP2_C_F64>), dim3(n), dim3(kThreads), 0, s, D, n, ld,
                                L.ldp, x0, x1, p0, p1, L.plane_stride, st);
@@ -271,8 +228,8 @@ static void finalize_t(T* D, int n, int ld, const Layout& L, sp2_compute mode, c
 }
 
 hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, sp2_compute mode,
-                           const State* st, const double* x0, const double* x1, const uint16_t* p0,
-                           const uint16_t* p1, hipStream_t s) {
+                           const State* st, const double* x0, const double* x1, const void* p0,
+                           const void* p1, hipStream_t s) {
     if (dt == SP2_F64) finalize_t<double>((double*)D, n, ld, L, mode, st, x0, x1, p0, p1, s);
     else finalize_t<float>((float*)D, n, ld, L, mode, st, x0, x1, p0, p1, s);
     return hipGetLastError();

@@ -127,7 +127,7 @@ const char* sp2_status_str(int status) {
 }
 
 static bool compute_built(sp2_compute c) {
-    return c == SP2_C_F64 || c == SP2_C_F16X2 || c == SP2_C_BF16X3 || c == SP2_C_BF16X2;
+    return c == SP2_C_F64 || c == SP2_C_F16X2 || c == SP2_C_BF16X3 || c == SP2_C_BF16X2 || c == SP2_C_FP8;
 }
 
 // FP64 steps before the split phase when the caller passes -1: enough for the
@@ -190,8 +190,8 @@ int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, i
     double* x1 = (double*)(ws + L.off_x1);
     unsigned* cnt = (unsigned*)(ws + L.off_cnt);
     double* scratch = (double*)(ws + L.off_scratch);
-    uint16_t* p0 = (uint16_t*)(ws + L.off_p0);
-    uint16_t* p1 = (uint16_t*)(ws + L.off_p1);
+    void* p0 = ws + L.off_p0;
+    void* p1 = ws + L.off_p1;
 
     HostSlots* hs = nullptr;
     Profile* prof = nullptr;
@@ -214,8 +214,8 @@ int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, i
             const int odd = issued & 1;
             double* xc = odd ? x1 : x0;
             double* xn = odd ? x0 : x1;
-            uint16_t* pc = odd ? p1 : p0;
-            uint16_t* pn = odd ? p0 : p1;
+            void* pc = odd ? p1 : p0;
+            void* pn = odd ? p0 : p1;
             hipEvent_t* ev = timed ? &prof->ev[2 * kLaunchesPerStep * issued] : nullptr;
             if (mixed && issued >= m0) {
                 // Both step kernels check the device state: exactly one of them

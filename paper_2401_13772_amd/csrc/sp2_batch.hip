@@ -39,6 +39,7 @@
 #include <string>
 #include <vector>
 
+#include "bounds_core.h"
 #include "syrk_f64_core.h"
 
 namespace sp2 {
@@ -49,6 +50,7 @@ struct BatchMat {
     double* x0;
     double* x1;
     double* part;
+    double* rowpart;   // Gershgorin row partials, (ldp / 64) x ldp
     State* st;
     int n, ldp, n_occ, pad;
 };
@@ -62,17 +64,16 @@ __global__ void k_batch_reset(BatchMat* mats, int batch, double tol, int max_ite
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     if (n_layers < 0) state_reset(mats[b].st, mats[b].n, mats[b].n_occ, tol, max_iter, 0);
-    else state_reset_learned(mats[b].st, mats[b].n, mats[b].n_occ, tol, n_layers, idem_fallback);
+    else state_reset_learned(mats[b].st, mats[b].n, mats[b].n_occ, tol, max_iter, n_layers, idem_fallback);
 }
 
 template <typename T>
 __device__ inline double ld_hb(const T* H, size_t idx) { return (double)H[idx]; }
 
-// One workgroup (kThreads) per matrix.  Bounds: the per-row radius of row i
-// is summed by four threads over 16-column strips of each 64-column tile, the
-// strips of 512 columns form one partial, partials are added in column order;
-// X_0 and its sums go tile by tile in row-major tile order.  These are the
-// orders of k_bounds_partial / k_bounds_final / k_init.
+// One workgroup (kThreads) per matrix, the tile pairs in order: the same
+// pair partials, row sums and pair sums as k_bounds_pair / k_bounds_final /
+// k_init_pair / k_init_final, added in the same order, so the plan's X_0 and
+// bounds equal sp2_density's bit for bit.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_batch_bounds_init(const BatchMat* __restrict__ mats) {
     __shared__ double sA[kBndTile][kBndTile + 1];
@@ -85,50 +86,29 @@ __global__ __launch_bounds__(kThreads) void k_batch_bounds_init(const BatchMat* 
     const int n = M.n, ld = M.n, ldp = M.ldp;
     State* st = M.st;
     const int tid = threadIdx.x;
-    const int r = tid >> 2, sub = tid & 3;
-    const int ncb = (n + kBndTile - 1) / kBndTile;
-    const int per = kBndColsPerBlock / kBndTile;
-    const int nsplit = (n + kBndColsPerBlock - 1) / kBndColsPerBlock;
+    const int nb = ldp / kBndTile;
+    const unsigned npairs = (unsigned)(nb * (nb + 1) / 2);
     if (tid == 0) sbad = 0;
-    double lo = INFINITY, hi = -INFINITY;
     int bad = 0;
-    for (int rb = 0; rb < ncb; ++rb) {
-        const int gi = rb * kBndTile + r;
-        double R = 0.0;
-        for (int split = 0; split < nsplit; ++split) {
-            double acc = 0.0;
-            const int cb1 = min(ncb, split * per + per);
-            for (int cb = split * per; cb < cb1; ++cb) {
-                for (int e = tid; e < kBndTile * kBndTile; e += kThreads) {
-                    const int rr = e >> 6, cc = e & 63;
-                    const int ra = rb * kBndTile + rr, ca = cb * kBndTile + cc;
-                    const int rbb = cb * kBndTile + rr, cbb = rb * kBndTile + cc;
-                    sA[rr][cc] = (ra < n && ca < n) ? ld_hb(H, (size_t)ra * ld + ca) : 0.0;
-                    sB[rr][cc] = (rbb < n && cbb < n) ? ld_hb(H, (size_t)rbb * ld + cbb) : 0.0;
-                }
-                __syncthreads();
-                for (int j = 0; j < 16; ++j) {
-                    const int c = sub * 16 + j;
-                    const int gj = cb * kBndTile + c;
-                    const double a = sA[r][c];
-                    const double b = sB[c][r];
-                    bad |= !isfinite(a);
-                    const double hs = (a + b) / 2.0;
-                    if (gj != gi && gj < n && gi < n) acc += fabs(hs);
-                }
-                __syncthreads();
-            }
-            acc += __shfl_xor(acc, 1, 64);
-            acc += __shfl_xor(acc, 2, 64);
-            R += acc;
-        }
-        if (sub == 0 && gi < n) {
-            const double c = ld_hb(H, (size_t)gi * ld + gi);
-            lo = fmin(lo, c - R);
-            hi = fmax(hi, c + R);
-        }
+    for (unsigned p = 0; p < npairs; ++p) {
+        int I, J;
+        tri_tile(p, I, J);
+        __syncthreads();
+        load_pair(H, n, ld, I, J, sA, sB, bad);
+        __syncthreads();
+        pair_row_partials(n, I, J, sA, sB, M.rowpart, ldp);
     }
     if (bad) atomicOr(&sbad, 1);
+    __threadfence();
+    __syncthreads();
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = tid; i < n; i += kThreads) {
+        double R = 0.0;
+        for (int K = 0; K < nb; ++K) R += M.rowpart[(size_t)K * ldp + i];
+        const double c = (double)H[(size_t)i * ld + i];
+        lo = fmin(lo, c - R);
+        hi = fmax(hi, c + R);
+    }
     lo = wave_min(lo);
     hi = wave_max(hi);
     const int w = tid >> 6;
@@ -139,52 +119,26 @@ __global__ __launch_bounds__(kThreads) void k_batch_bounds_init(const BatchMat* 
     __syncthreads();
     const double emin = fmin(fmin(red[0][0], red[0][1]), fmin(red[0][2], red[0][3]));
     const double emax = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
-    const double width = emax - emin;
     if (tid == 0) {
         st->emin = emin;
         st->emax = emax;
         st->bad = sbad;
     }
-    // X_0, tile by tile (the partner tile of (H + H^T)/2 through LDS)
-    const int nb = ldp / kBndTile;
-    double* part = M.part;
-    for (int bi = 0; bi < nb; ++bi)
-        for (int bj = 0; bj < nb; ++bj) {
-            __syncthreads();
-            for (int e = tid; e < kBndTile * kBndTile; e += kThreads) {
-                const int rr = e >> 6, cc = e & 63;
-                const int gr = bj * kBndTile + rr, gc = bi * kBndTile + cc;
-                sB[rr][cc] = (gr < n && gc < n) ? ld_hb(H, (size_t)gr * ld + gc) : 0.0;
-            }
-            __syncthreads();
-            double trp = 0.0, fro = 0.0;
-            for (int e = tid; e < kBndTile * kBndTile; e += kThreads) {
-                const int rr = e >> 6, cc = e & 63;
-                const int gi = bi * kBndTile + rr, gj = bj * kBndTile + cc;
-                double x = 0.0;
-                if (gi < n && gj < n) {
-                    const double a = ld_hb(H, (size_t)gi * ld + gj);
-                    const double hs = (a + sB[cc][rr]) / 2.0;
-                    const double num = (gi == gj) ? (emax - hs) : (0.0 - hs);
-                    x = num / width;
-                }
-                M.x0[(size_t)gi * ldp + gj] = x;
-                fro += x * x;
-                if (gi == gj) trp += x;
-            }
-            trp = block_sum(trp, bred);
-            fro = block_sum(fro, bred);
-            if (tid == 0) {
-                part[2 * (bi * nb + bj) + 0] = trp;
-                part[2 * (bi * nb + bj) + 1] = fro;
-            }
-        }
+    const double width = emax - emin;
+    for (unsigned p = 0; p < npairs; ++p) {
+        int I, J;
+        tri_tile(p, I, J);
+        __syncthreads();
+        load_pair(H, n, ld, I, J, sA, sB, bad);
+        __syncthreads();
+        pair_x0(n, ldp, I, J, emax, width, sA, sB, M.x0, bred, M.part, p);
+    }
     __threadfence();
     __syncthreads();
     double t = 0.0, f = 0.0;
-    for (int k = tid; k < nb * nb; k += kThreads) {
-        t += part[2 * k + 0];
-        f += part[2 * k + 1];
+    for (unsigned k = tid; k < npairs; k += kThreads) {
+        t += M.part[2 * k + 0];
+        f += M.part[2 * k + 1];
     }
     t = block_sum(t, bred);
     f = block_sum(f, bred);
@@ -494,7 +448,8 @@ namespace sp2 {
 
 // The plan behind sp2_plan_create and the learned expansion's inference:
 // n_layers < 0 is plain SP2; otherwise coef (3 per layer) are the trained
-// layers, max_iter is n_layers + 1 and the check step uses idem_fallback.
+// layers, followed by the check step (bar idem_fallback) and plain SP2 steps
+// up to max_iter steps in all.
 int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ, sp2_dtype dtype,
                      sp2_compute compute, double tol, int max_iter, const char* autotune_cache,
                      const double* coef, int n_layers, double idem_fallback) {
@@ -503,7 +458,7 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
     if (batch <= 0 || batch > SP2_PLAN_MAX_BATCH || !n || !n_occ) return SP2_E_INVALID;
     if (dtype != SP2_F64 && dtype != SP2_F32) return SP2_E_INVALID;
     if (!(tol > 0.0) || !(tol < 1e300) || max_iter < 0 || max_iter > SP2_MAX_ITER) return SP2_E_INVALID;
-    if (n_layers >= 0 && (n_layers + 1 > SP2_MAX_ITER || (n_layers > 0 && !coef) || !(idem_fallback > 0.0)))
+    if (n_layers >= 0 && (n_layers + 1 > max_iter || (n_layers > 0 && !coef) || !(idem_fallback > 0.0)))
         return SP2_E_INVALID;
     if (compute < SP2_C_F64 || compute > SP2_C_FP8) return SP2_E_INVALID;
     if (compute != SP2_C_F64) return SP2_E_UNSUPPORTED;
@@ -516,7 +471,7 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
     p->dtype = dtype;
     p->compute = compute;
     p->tol = tol;
-    p->max_iter = n_layers >= 0 ? n_layers + 1 : max_iter;
+    p->max_iter = max_iter;
     p->n_layers = n_layers;
     p->idem_fallback = idem_fallback;
     p->n.assign(n, n + batch);
@@ -545,11 +500,13 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
     const size_t off_tune = off;  off = up256(off + max_items * sizeof(int2));
     const size_t off_st = off;    off = up256(off + batch * up256(sizeof(State)));
     const size_t off_coef = off;  off = up256(off + (size_t)3 * (n_layers > 0 ? n_layers : 1) * sizeof(double));
-    std::vector<size_t> off_part(batch), off_x(batch);
+    std::vector<size_t> off_part(batch), off_x(batch), off_rp(batch);
     for (int k = 0; k < batch; ++k) {
         const int T32 = ldp[k] / 32;                 // the finest candidate tiling
         off_part[k] = off;
         off = up256(off + (size_t)4 * T32 * (T32 + 1) / 2 * sizeof(double));
+        off_rp[k] = off;
+        off = up256(off + (size_t)(ldp[k] / kBndTile) * ldp[k] * sizeof(double));
     }
     for (int k = 0; k < batch; ++k) {
         off_x[k] = off;
@@ -573,6 +530,7 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
         m.D = nullptr;
         m.st = (State*)(base + off_st + k * up256(sizeof(State)));
         m.part = (double*)(base + off_part[k]);
+        m.rowpart = (double*)(base + off_rp[k]);
         m.x0 = (double*)(base + off_x[k]);
         m.x1 = m.x0 + (size_t)ldp[k] * ldp[k];
         m.n = n[p->order[k]];

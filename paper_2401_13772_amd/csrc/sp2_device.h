@@ -3,6 +3,8 @@
 // encodings and the device-side steering of the SP2 loop.
 #pragma once
 
+#include <hip/hip_fp8.h>
+
 #include "sp2_internal.h"
 
 namespace sp2 {
@@ -64,7 +66,8 @@ __device__ inline bool group_arrive_last(unsigned* ticket, unsigned nblocks, int
 //           out of FP16's subnormal range, ~22 significant bits for |x| down
 //           to 2^-14 and an absolute quantum of 2^-35 below);
 //   BF16X3: x ~ b1 + b2 + b3, each plane bf16 of the remainder (~24 bits);
-//   BF16X2: x ~ b1 + b2                                      (~16 bits).
+//   BF16X2: x ~ b1 + b2                                      (~16 bits);
+//   FP8X2 : two e4m3 planes with power-of-two scales (below)   (~8 bits).
 // Products: the leading term hi*hi is accumulated apart from the correction
 // terms (hi*lo + lo*hi, and for BF16X3 the next order), because it alone is
 // O(|S|) and sets the FP32 rounding level; see syrk_lp.hip.  LO_SCALE is the
@@ -74,7 +77,9 @@ template <int MODE> struct Planes;
 
 template <> struct Planes<SP2_C_F16X2> {
     static constexpr int NP = 2;
+    static constexpr double HI_SCALE = 1.0;
     static constexpr double LO_SCALE = 1.0 / 2048.0;
+    typedef uint16_t Elem;
     typedef _Float16 T;
     __device__ static inline void encode(double x, uint16_t* out) {
         const _Float16 h = (_Float16)x;
@@ -92,7 +97,9 @@ __device__ inline __bf16 to_bf16(double x) { return (__bf16)(float)x; }
 
 template <> struct Planes<SP2_C_BF16X3> {
     static constexpr int NP = 3;
+    static constexpr double HI_SCALE = 1.0;
     static constexpr double LO_SCALE = 1.0;
+    typedef uint16_t Elem;
     typedef __bf16 T;
     __device__ static inline void encode(double x, uint16_t* out) {
         const __bf16 b1 = to_bf16(x);
@@ -112,7 +119,9 @@ template <> struct Planes<SP2_C_BF16X3> {
 
 template <> struct Planes<SP2_C_BF16X2> {
     static constexpr int NP = 2;
+    static constexpr double HI_SCALE = 1.0;
     static constexpr double LO_SCALE = 1.0;
+    typedef uint16_t Elem;
     typedef __bf16 T;
     __device__ static inline void encode(double x, uint16_t* out) {
         const __bf16 b1 = to_bf16(x);
@@ -126,19 +135,47 @@ template <> struct Planes<SP2_C_BF16X2> {
     }
 };
 
+// FP8X2: two OCP e4m3 planes with fixed power-of-two scales,
+//   x ~ 2^-8 q0 + 2^-12 q1,  q0 = e4m3(2^8 x),  q1 = e4m3(2^12 (x - 2^-8 q0)).
+// SP2 iterates satisfy |x| <= 1, so 2^8 x stays inside e4m3's range (448);
+// e4m3 keeps 4 significant bits, so q1 takes the next 4 (~8 bits in all, a
+// BF16X2-class representation).  Products q_i q_j carry 2^-(16 + 4(i+j)).
+template <> struct Planes<SP2_C_FP8> {
+    static constexpr int NP = 2;
+    static constexpr double HI_SCALE = 1.0 / 65536.0;      // 2^-16
+    static constexpr double LO_SCALE = 1.0 / 1048576.0;    // 2^-20
+    typedef uint8_t Elem;
+    __device__ static inline uint8_t to_e4m3(double v) {
+        return (uint8_t)__hip_cvt_float_to_fp8((float)v, __HIP_SATFINITE, __HIP_E4M3);
+    }
+    __device__ static inline double from_e4m3(uint8_t q) {
+        const __half_raw h = __hip_cvt_fp8_to_halfraw((__hip_fp8_storage_t)q, __HIP_E4M3);
+        return (double)__builtin_bit_cast(_Float16, h.x);
+    }
+    __device__ static inline void encode(double x, uint8_t* out) {
+        const uint8_t q0 = to_e4m3(x * 256.0);
+        const double r = x - from_e4m3(q0) * (1.0 / 256.0);
+        out[0] = q0;
+        out[1] = to_e4m3(r * 4096.0);
+    }
+    __device__ static inline double decode(const uint8_t* in) {
+        return from_e4m3(in[0]) * (1.0 / 256.0) + from_e4m3(in[1]) * (1.0 / 4096.0);
+    }
+};
+
 // Write the planes of value x at element offset `idx` (plane p lives at
 // base + p * pstride).
 template <int MODE>
-__device__ inline void store_planes(uint16_t* base, size_t pstride, size_t idx, double x) {
-    uint16_t v[Planes<MODE>::NP];
+__device__ inline void store_planes(typename Planes<MODE>::Elem* base, size_t pstride, size_t idx, double x) {
+    typename Planes<MODE>::Elem v[Planes<MODE>::NP];
     Planes<MODE>::encode(x, v);
 #pragma unroll
     for (int p = 0; p < Planes<MODE>::NP; ++p) base[p * pstride + idx] = v[p];
 }
 
 template <int MODE>
-__device__ inline double load_planes(const uint16_t* base, size_t pstride, size_t idx) {
-    uint16_t v[Planes<MODE>::NP];
+__device__ inline double load_planes(const typename Planes<MODE>::Elem* base, size_t pstride, size_t idx) {
+    typename Planes<MODE>::Elem v[Planes<MODE>::NP];
 #pragma unroll
     for (int p = 0; p < Planes<MODE>::NP; ++p) v[p] = base[p * pstride + idx];
     return Planes<MODE>::decode(v);
@@ -182,11 +219,12 @@ __device__ inline void state_reset(State* st, int n, int n_occ, double tol, int 
     st->idem_fallback = 0.0;
 }
 
-// Start of a learned-expansion solve: n_layers trained layers, then one SP2
-// step whose idempotency decides between OK and SP2_E_FALLBACK.
-__device__ inline void state_reset_learned(State* st, int n, int n_occ, double tol, int n_layers,
-                                           double idem_fallback) {
-    state_reset(st, n, n_occ, tol, n_layers + 1, 0);
+// Start of a learned-expansion solve: n_layers trained layers, then an SP2
+// check step that accepts, continues with plain SP2 up to max_iter steps in
+// all, or stops for a restart from H.
+__device__ inline void state_reset_learned(State* st, int n, int n_occ, double tol, int max_iter,
+                                           int n_layers, double idem_fallback) {
+    state_reset(st, n, n_occ, tol, max_iter, 0);
     st->n_layers = n_layers;
     st->idem_fallback = idem_fallback;
     st->phase = n_layers > 0 ? 3 : 4;
@@ -299,6 +337,7 @@ __device__ __forceinline__ void sp2_steer_thread0(State* st, double E, double TR
         }
     } else if (phase == 3) {
         // trained layers: steered by the trace, no stop test but convergence
+        st->fp64_steps = st->fp64_steps + 1;
         st->grow = trace_grow;
         if (e <= st->tol) {
             st->done = 1;
@@ -307,11 +346,36 @@ __device__ __forceinline__ void sp2_steer_thread0(State* st, double E, double TR
             st->phase = 4;
         }
     } else if (phase == 4) {
-        // the SP2 check step: e is the idempotency of the last layer's output
+        // the SP2 check step: e is the idempotency of the last layer's output.
+        // Accepted: done.  Close to a projector (every eigenvalue x has
+        // |x^2 - x| <= 0.25, so x lies in (-0.21, 1.21), where trace-steered
+        // SP2 steps pull it to 0 or 1): plain SP2 steps go on from here.
+        // Otherwise the solve stops for a restart from H (SP2_E_FALLBACK).
         st->grow = trace_grow;
-        st->done = 1;
         const double terr = fabs(TR - st->nocc);
-        st->status = (e <= st->idem_fallback && terr <= st->idem_fallback) ? SP2_OK : SP2_E_FALLBACK;
+        if (e <= st->idem_fallback && terr <= st->idem_fallback) {
+            st->done = 1;
+            st->status = SP2_OK;
+        } else if (e <= 0.25 && m + 1 < st->max_iter) {
+            st->phase = 5;
+        } else {
+            st->done = 1;
+            st->status = SP2_E_FALLBACK;
+        }
+    } else if (phase == 5) {
+        // plain SP2 after the learned layers (the stop rule of phase 0)
+        st->refine_steps = st->refine_steps + 1;
+        st->grow = trace_grow;
+        if (e <= st->tol) {
+            st->done = 1;
+            st->status = SP2_OK;
+        } else if (m >= 2 && e >= st->e_hist[m - 2] && e < 0.1) {
+            st->done = 1;
+            st->status = SP2_E_STAGNATED;
+        } else if (m + 1 >= st->max_iter) {
+            st->done = 1;
+            st->status = SP2_E_NOT_CONVERGED;
+        }
     } else {
         st->stale = 0;
         st->refine_steps = st->refine_steps + 1;

@@ -11,7 +11,6 @@ namespace sp2 {
 
 constexpr int kThreads = 256;        // every kernel uses 4 wave64s per workgroup
 constexpr int kBndTile = 64;         // tile edge of the bounds / init / finalize kernels
-constexpr int kBndColsPerBlock = 512;
 constexpr int kMaxPersistent = 1024; // upper bound on the stream-K grid
 
 // Loop state, resident in the workspace.  Written by the last-arriving block
@@ -59,7 +58,8 @@ struct Layout {
     int n, ldp, bt;          // padded edge, FP64 SYRK tile edge
     int tiles;               // lower tiles of the FP64 SYRK grid
     int max_groups;          // stream-K grid bound: min(tiles, kMaxPersistent)
-    int np;                  // 16-bit planes per iterate (0: FP64 only)
+    int np;                  // split-operand planes per iterate (0: FP64 only)
+    int pb;                  // bytes per plane element
     size_t plane_stride;     // elements between planes of one iterate (ldp^2)
     size_t off_state, off_part, off_rowpart, off_cnt, off_scratch, off_x0, off_x1;
     size_t off_p0, off_p1, total;
@@ -68,8 +68,11 @@ struct Layout {
 constexpr int kLpTile = 128;  // tile edge of the split-operand kernels
 
 inline int planes_of(sp2_compute c) {
-    return c == SP2_C_F16X2 ? 2 : c == SP2_C_BF16X3 ? 3 : c == SP2_C_BF16X2 ? 2 : 0;
+    return c == SP2_C_F16X2 ? 2 : c == SP2_C_BF16X3 ? 3 : c == SP2_C_BF16X2 ? 2 : c == SP2_C_FP8 ? 2 : 0;
 }
+
+// bytes per plane element (FP8 planes are one byte)
+inline int plane_elem_bytes(sp2_compute c) { return c == SP2_C_FP8 ? 1 : 2; }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -81,6 +84,7 @@ inline Layout make_layout(int n, sp2_compute compute) {
     L.n = n;
     L.bt = syrk_tile(n);
     L.np = planes_of(compute);
+    L.pb = plane_elem_bytes(compute);
     L.ldp = (int)align_up((size_t)n, (size_t)(L.np ? kLpTile : L.bt));
     L.plane_stride = (size_t)L.ldp * L.ldp;
     int T = L.ldp / L.bt;
@@ -89,14 +93,14 @@ inline Layout make_layout(int n, sp2_compute compute) {
     size_t part_entries = (size_t)L.tiles * 4;
     size_t init_entries = (size_t)nb * nb * 4;
     if (init_entries > part_entries) part_entries = init_entries;
-    int nsplit = (n + kBndColsPerBlock - 1) / kBndColsPerBlock;
+    const int nbt = L.ldp / kBndTile;   // 64-row tiles of the bounds / X_0 kernels
     // the 128-tile FP64 kernel runs up to kMaxPersistent workgroups whatever
     // the tile count (its stream-K remainder spreads a few tiles over many)
     L.max_groups = (L.bt == 128 || L.tiles > kMaxPersistent) ? kMaxPersistent : L.tiles;
     size_t off = 0;
     L.off_state = off;   off = align_up(off + sizeof(State), 256);
     L.off_part = off;    off = align_up(off + part_entries * sizeof(double), 256);
-    L.off_rowpart = off; off = align_up(off + ((size_t)nsplit * L.ldp + 2 * (size_t)L.ldp) * sizeof(double), 256);
+    L.off_rowpart = off; off = align_up(off + ((size_t)nbt * L.ldp + 2 * (size_t)L.ldp) * sizeof(double), 256);
     size_t scratch_f64 = 2 * (size_t)(L.max_groups + 1) * L.bt * L.bt * sizeof(double);
     int Tl = L.ldp / kLpTile;
     int lp_groups = Tl * (Tl + 1) / 2 < kMaxPersistent ? Tl * (Tl + 1) / 2 : kMaxPersistent;
@@ -106,8 +110,8 @@ inline Layout make_layout(int n, sp2_compute compute) {
     L.off_scratch = off; off = align_up(off + (scratch_f64 > scratch_lp ? scratch_f64 : scratch_lp), 256);
     L.off_x0 = off;      off = align_up(off + (size_t)L.ldp * L.ldp * sizeof(double), 256);
     L.off_x1 = off;      off = align_up(off + (size_t)L.ldp * L.ldp * sizeof(double), 256);
-    L.off_p0 = off;      off = align_up(off + (size_t)L.np * L.plane_stride * sizeof(uint16_t), 256);
-    L.off_p1 = off;      off = align_up(off + (size_t)L.np * L.plane_stride * sizeof(uint16_t), 256);
+    L.off_p0 = off;      off = align_up(off + (size_t)L.np * L.plane_stride * L.pb, 256);
+    L.off_p1 = off;      off = align_up(off + (size_t)L.np * L.plane_stride * L.pb, 256);
     L.total = off;
     return L;
 }
@@ -183,13 +187,13 @@ hipError_t launch_init(const void* H, sp2_dtype dt, int n, int ld, const Layout&
                        double* x0, double* part, hipStream_t s);
 hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* st, double* part,
                            double* scratch, unsigned* cnt, int step, hipStream_t s);
-hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const uint16_t* Pin, uint16_t* Pout,
+hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const void* Pin, void* Pout,
                           double* X, State* st, double* part, double* scratch, unsigned* cnt,
                           int step, hipStream_t s);
-hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, uint16_t* Pout,
+hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, void* Pout,
                                 const State* st, int step, hipStream_t s);
 hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, sp2_compute mode,
-                           const State* st, const double* x0, const double* x1, const uint16_t* p0,
-                           const uint16_t* p1, hipStream_t s);
+                           const State* st, const double* x0, const double* x1, const void* p0,
+                           const void* p1, hipStream_t s);
 
 }  // namespace sp2

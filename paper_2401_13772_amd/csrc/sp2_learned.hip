@@ -19,10 +19,13 @@
 // step).
 //
 // Inference (sp2_learned_density) is the batched plan with the trained
-// coefficients in the step kernel's epilogue, followed by one SP2 step whose
-// idempotency (and the trace error) decides acceptance; rejected matrices are
-// solved again from H by plain SP2 (sp2_density) and reported as
-// SP2_E_FALLBACK.
+// coefficients in the step kernel's epilogue, followed by an SP2 check step
+// whose idempotency (and trace error) decides: accept; or, when the output is
+// close to a projector, hand over to plain SP2 steps on the device (the layers
+// then act as a faster gap-opening prefix); or solve again from H by plain SP2
+// (sp2_density), reported as SP2_E_FALLBACK.  Training clamps values to
+// [-4, 5] (a diverging sample then has a large but finite loss) and clips the
+// gradient to norm 10.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -48,6 +51,7 @@ struct sp2_learned {
 namespace sp2 {
 
 constexpr int kLearnMaxLayers = 64;
+constexpr int kContinueSteps = 60;   // plain SP2 steps allowed after the layers
 constexpr int kLearnMaxN = 1024;
 
 // One sample per workgroup.  lam: spectra (ascending) of all samples,
@@ -87,7 +91,9 @@ __global__ __launch_bounds__(kThreads) void k_learned_grad(const double* __restr
         for (int i = tid; i < n; i += kThreads, ++q) {
             const double u = p ? 1.0 - x[i] : x[i];
             const double y = a * u * u + b * u + c;
-            const double v = p ? 1.0 - y : y;
+            // guard: a composition of quadratics overflows once a value leaves
+            // the basin; such samples have a large loss anyway
+            const double v = fmin(fmax(p ? 1.0 - y : y, -4.0), 5.0);
             if (k + 1 < L) hist[(size_t)(k + 1) * n + i] = v;
             else xout[q] = v;
         }
@@ -244,7 +250,7 @@ int sp2_learned_fit(sp2_learned** model, int n_layers, const double* spectra, co
     std::vector<double> g((size_t)B * 3 * L), lossv(B);
     uint64_t rng = seed;
     long t = 0;
-    double lr = 3e-3, last_loss = 0.0;
+    double lr = 1e-3, last_loss = 0.0;
     const int per_epoch = (n_samples + B - 1) / B;
     for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
         for (int s = n_samples - 1; s > 0; --s) {    // Fisher-Yates with splitmix64
@@ -268,10 +274,18 @@ int sp2_learned_fit(sp2_learned** model, int n_layers, const double* spectra, co
             if (e == hipSuccess) e = hipMemcpy(lossv.data(), d_loss, nb * sizeof(double), hipMemcpyDeviceToHost);
             if (e != hipSuccess) break;
             ++t;
+            std::vector<double> gsum(coef.size(), 0.0);
+            double gn = 0.0;
             for (size_t q = 0; q < coef.size(); ++q) {
-                double gs = 0.0;
-                for (int b = 0; b < nb; ++b) gs += g[(size_t)b * 3 * L + q];   // sample order
-                gs /= nb;
+                for (int b = 0; b < nb; ++b) gsum[q] += g[(size_t)b * 3 * L + q];   // sample order
+                gsum[q] /= nb;
+                gn += gsum[q] * gsum[q];
+            }
+            gn = std::sqrt(gn);
+            if (!std::isfinite(gn)) continue;                  // skip a step that overflowed
+            const double clip = gn > 10.0 ? 10.0 / gn : 1.0;   // global-norm clipping
+            for (size_t q = 0; q < coef.size(); ++q) {
+                const double gs = gsum[q] * clip;
                 mom[q] = 0.9 * mom[q] + 0.1 * gs;
                 var[q] = 0.999 * var[q] + 0.001 * gs * gs;
                 const double mh = mom[q] / (1.0 - std::pow(0.9, (double)t));
@@ -282,7 +296,7 @@ int sp2_learned_fit(sp2_learned** model, int n_layers, const double* spectra, co
             ep_cnt += nb;
         }
         last_loss = ep_cnt ? ep_loss / ep_cnt : 0.0;
-        if ((ep + 1) % 25 == 0) lr *= 0.8;
+        if (epochs >= 10 && (ep + 1) % (epochs / 10) == 0) lr *= 0.8;
     }
     (void)hipFree(dmem);
     if (e != hipSuccess) return SP2_E_HIP;
@@ -345,8 +359,10 @@ int sp2_learned_density(sp2_learned* model, int batch, int n, const void* const*
         if (model->plan) sp2_plan_destroy(model->plan);
         model->plan = nullptr;
         std::vector<int> ns(batch, n);
-        const int st = sp2::plan_create_impl(&model->plan, batch, ns.data(), n_occ, dtype, SP2_C_F64, 1e-300,
-                                             model->n_layers + 1, nullptr, model->coef.data(), model->n_layers,
+        int max_iter = model->n_layers + 1 + sp2::kContinueSteps;
+        if (max_iter > SP2_MAX_ITER) max_iter = SP2_MAX_ITER;
+        const int st = sp2::plan_create_impl(&model->plan, batch, ns.data(), n_occ, dtype, SP2_C_F64, 1e-10,
+                                             max_iter, nullptr, model->coef.data(), model->n_layers,
                                              idem_fallback);
         if (st != SP2_OK) return st;
         model->key_batch = batch;
@@ -373,9 +389,10 @@ int sp2_learned_density(sp2_learned* model, int batch, int n, const void* const*
             sp2_info r{};
             const int s2 = sp2_density(H[b], D[b], n, n, n_occ[b], 1e-10, 100, dtype, SP2_C_F64, -1, model->fb_ws,
                                        model->fb_ws_bytes, hip_stream, &r);
-            const int layers_done = inf[b].iterations;
+            const int layers_done = inf[b].fp64_prefix_iters;
             inf[b] = r;
-            inf[b].refine_steps = layers_done;   // the rejected learned pass
+            inf[b].fp64_prefix_iters = layers_done;   // the rejected learned pass
+            inf[b].refine_steps = r.iterations;       // the plain SP2 solve from H
             if (s2 == SP2_OK) inf[b].status = SP2_E_FALLBACK;
         }
         if (inf[b].status < worst_neg) worst_neg = inf[b].status;

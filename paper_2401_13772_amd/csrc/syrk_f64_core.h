@@ -28,14 +28,17 @@ using CfgLarge = SyrkCfg<128, 2, 4>;   // 512 threads, 64 x 32 per wave
 
 // Accumulate the C tile over K slices [kt0, kt1) of the row panels of tiles
 // ti and tj.  DIAG: ti == tj, both operands come from one panel.
+// Two-operand form: the row panels of tile ti come from XA, those of tj from
+// XB (C = XA XB^T, equal to XA XB for symmetric XB); DIAG (same matrix and
+// ti == tj) reads one panel.
 template <class C, bool DIAG>
-__device__ __forceinline__ void syrk_mainloop(const double* __restrict__ X, int ldp, int ti, int tj,
-                                              int kt0, int kt1, double* sA, double* sB,
-                                              d4 (&acc)[C::MI][C::NI]) {
+__device__ __forceinline__ void syrk_mainloop2(const double* __restrict__ XA, const double* __restrict__ XB,
+                                               int ldp, int ti, int tj, int kt0, int kt1, double* sA, double* sB,
+                                               d4 (&acc)[C::MI][C::NI]) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w / C::WN, wn = w % C::WN;
-    const double* Ap = X + (size_t)ti * C::BT * ldp;
-    const double* Bp = X + (size_t)tj * C::BT * ldp;
+    const double* Ap = XA + (size_t)ti * C::BT * ldp;
+    const double* Bp = XB + (size_t)tj * C::BT * ldp;
     int goff[C::LOADS], soff[C::LOADS];
 #pragma unroll
     for (int i = 0; i < C::LOADS; ++i) {
@@ -102,6 +105,13 @@ __device__ __forceinline__ void syrk_mainloop(const double* __restrict__ X, int 
         }
         __syncthreads();
     }
+}
+
+template <class C, bool DIAG>
+__device__ __forceinline__ void syrk_mainloop(const double* __restrict__ X, int ldp, int ti, int tj,
+                                              int kt0, int kt1, double* sA, double* sB,
+                                              d4 (&acc)[C::MI][C::NI]) {
+    syrk_mainloop2<C, DIAG>(X, X, ldp, ti, tj, kt0, kt1, sA, sB, acc);
 }
 
 // The SP2 update of one finished C tile, and this thread's share of the

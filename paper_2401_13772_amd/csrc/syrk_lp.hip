@@ -13,7 +13,7 @@
 //   * the correction terms hi*lo + lo*hi (+ the next order for BF16 x3), in
 //     an FP32 accumulator of their own: they are 2^-11 (2^-8) of |S|, so
 //     their FP32 rounding is far below the plane rounding of X'.
-// S = acc64 + LO_SCALE * acc32.  The epilogue is the same SP2 update as the
+// S = HI_SCALE * acc64 + LO_SCALE * acc32.  The epilogue is the same SP2 update as the
 // FP64 step (Section "SP2 solver": X' = X^2 or 2X - X^2 by the trace),
 // evaluated in FP64 from the decoded X and S; it writes the planes of X'
 // (they are the iterate during this phase: no FP64 copy is stored) and the
@@ -38,9 +38,11 @@ namespace sp2 {
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+typedef long l1 __attribute__((ext_vector_type(1)));
 
-constexpr int kLBK = 32;  // K slice in 16-bit elements (64 bytes per row)
+// A K slice is 64 bytes of every row of a plane: 32 elements of the 16-bit
+// formats, 64 of FP8.
+constexpr int kSliceBytes = 64;
 
 template <int BT_, int WM_, int WN_, int MODE_>
 struct LpCfg {
@@ -49,7 +51,9 @@ struct LpCfg {
     static constexpr int WTM = BT / WM, WTN = BT / WN;
     static constexpr int MI = WTM / 16, NI = WTN / 16;
     static constexpr int NP = Planes<MODE>::NP;
-    static constexpr int PANEL_BYTES = BT * kLBK * 2;          // one plane of one panel
+    typedef typename Planes<MODE>::Elem Elem;
+    static constexpr int KE = kSliceBytes / (int)sizeof(Elem); // elements per K slice
+    static constexpr int PANEL_BYTES = BT * kSliceBytes;       // one plane of one panel
     static constexpr int STAGE_BYTES = NP * 2 * PANEL_BYTES;
     static constexpr int CLD = BT + 1;                          // padded row of the LDS S tile (doubles)
     static constexpr size_t CTILE = (size_t)BT * CLD * sizeof(double);
@@ -60,19 +64,29 @@ struct LpCfg {
     static_assert(LDS <= 160 * 1024, "LDS budget of one CU");
 };
 
+// The product of one 16-byte fragment pair: 8 elements of each of the lane's
+// rows for the 16-bit formats (one MFMA), 16 for FP8 (two MFMAs on the low
+// and high 8 bytes; A and B use the same split of k, so the sum covers every
+// k of the slice once).
 template <int MODE>
 __device__ __forceinline__ f4 mfma16(const uint4& a, const uint4& b, f4 c) {
-    if constexpr (MODE == SP2_C_F16X2)
+    if constexpr (MODE == SP2_C_F16X2) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
-    else
+    } else if constexpr (MODE == SP2_C_FP8) {
+        const long alo = (long)(((unsigned long)a.y << 32) | a.x), ahi = (long)(((unsigned long)a.w << 32) | a.z);
+        const long blo = (long)(((unsigned long)b.y << 32) | b.x), bhi = (long)(((unsigned long)b.w << 32) | b.z);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(alo, blo, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ahi, bhi, c, 0, 0, 0);
+    } else {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), c, 0, 0, 0);
+    }
 }
 
 __device__ __forceinline__ int swz(int row) { return (row >> 1) & 3; }
 
 // Issue the LDS-DMA loads of one K slice (all planes, both panels) into `stage`.
 template <class C, bool DIAG>
-__device__ __forceinline__ void lp_issue(const uint16_t* __restrict__ P, size_t pstride, int ldp,
+__device__ __forceinline__ void lp_issue(const typename C::Elem* __restrict__ P, size_t pstride, int ldp,
                                          int rowA, int rowB, int k0, char* stage) {
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -86,7 +100,8 @@ __device__ __forceinline__ void lp_issue(const uint16_t* __restrict__ P, size_t 
                 const int blk = w * C::BPW + j;
                 const int row = blk * 16 + (lane >> 2);
                 const int c = (lane & 3) ^ swz(row);
-                const uint16_t* src = P + p * pstride + (size_t)(prow0 + row) * ldp + k0 + 8 * c;
+                const typename C::Elem* src = P + p * pstride + (size_t)(prow0 + row) * ldp + k0 +
+                                              c * (16 / (int)sizeof(typename C::Elem));
                 char* dst = stage + (p * 2 + q) * C::PANEL_BYTES + blk * 1024;
                 __builtin_amdgcn_global_load_lds((const void*)src,
                                                  (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
@@ -96,13 +111,13 @@ __device__ __forceinline__ void lp_issue(const uint16_t* __restrict__ P, size_t 
 }
 
 template <class C, bool DIAG>
-__device__ __forceinline__ void lp_mainloop(const uint16_t* __restrict__ P, size_t pstride, int ldp,
+__device__ __forceinline__ void lp_mainloop(const typename C::Elem* __restrict__ P, size_t pstride, int ldp,
                                             int ti, int tj, int kt0, int kt1, char* smem,
                                             d4 (&acc)[C::MI][C::NI], f4 (&accx)[C::MI][C::NI]) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w / C::WN, wn = w % C::WN;
     const int rowA = ti * C::BT, rowB = tj * C::BT;
-    lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, kt0 * kLBK, smem);
+    lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, kt0 * C::KE, smem);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     // fragment addressing: row r of the wave's sub-tile, chunk c = lane >> 4
@@ -121,7 +136,7 @@ __device__ __forceinline__ void lp_mainloop(const uint16_t* __restrict__ P, size
     for (int kt = kt0; kt < kt1; ++kt) {
         const int stg = (kt - kt0) & 1;
         if (kt + 1 < kt1)
-            lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, (kt + 1) * kLBK, smem + (stg ^ 1) * C::STAGE_BYTES);
+            lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, (kt + 1) * C::KE, smem + (stg ^ 1) * C::STAGE_BYTES);
         const char* S = smem + stg * C::STAGE_BYTES;
         uint4 af[C::NP][C::MI], bf[C::NP][C::NI];
 #pragma unroll
@@ -181,7 +196,8 @@ __device__ __forceinline__ void lp_acc_to_lds(const d4 (&acc)[C::MI][C::NI], con
             const int c = wn * C::WTN + ni * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                Cs[(r0 + r) * C::CLD + c] = acc[mi][ni][r] + Planes<C::MODE>::LO_SCALE * (double)accx[mi][ni][r];
+                Cs[(r0 + r) * C::CLD + c] = Planes<C::MODE>::HI_SCALE * acc[mi][ni][r] +
+                                            Planes<C::MODE>::LO_SCALE * (double)accx[mi][ni][r];
         }
 }
 
@@ -195,13 +211,15 @@ __device__ __forceinline__ void lp_acc_to_lds(const d4 (&acc)[C::MI][C::NI], con
 //           are bitwise symmetric, so X' comes out bit-identical).
 // Diagonal tiles take the lower triangle's S for both halves.
 template <class C>
-__device__ __forceinline__ void lp_epilogue(const uint16_t* __restrict__ Pin, uint16_t* __restrict__ Pout,
+__device__ __forceinline__ void lp_epilogue(const typename C::Elem* __restrict__ Pin,
+                                            typename C::Elem* __restrict__ Pout,
                                             size_t pstride, int ldp, int ti, int tj, int grow,
                                             const double* Cs, double& e2, double& trp, double& fro) {
     constexpr int RUN = 8;
     constexpr int RUNS_PER_ROW = C::BT / RUN;
     const bool diag = (ti == tj);
-    typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+    typedef typename C::Elem E;
+    typedef E u16x8 __attribute__((ext_vector_type(8)));
     for (int pass = 0; pass < (diag ? 1 : 2); ++pass) {
         const int rbase = (pass == 0 ? ti : tj) * C::BT;
         const int cbase = (pass == 0 ? tj : ti) * C::BT;
@@ -219,7 +237,7 @@ __device__ __forceinline__ void lp_epilogue(const uint16_t* __restrict__ Pin, ui
                 if (pass == 1) sd = Cs[c * C::CLD + r];                        // mirrored tile
                 else if (diag && c > r) sd = Cs[c * C::CLD + r];               // upper half of a diagonal tile
                 else sd = Cs[r * C::CLD + c];
-                uint16_t v[C::NP];
+                E v[C::NP];
 #pragma unroll
                 for (int p = 0; p < C::NP; ++p) v[p] = xin[p][k];
                 const double x = Planes<C::MODE>::decode(v);
@@ -231,7 +249,7 @@ __device__ __forceinline__ void lp_epilogue(const uint16_t* __restrict__ Pin, ui
                     fro += wgt * (xn * xn);
                     if (diag && c == r) trp += xn;
                 }
-                uint16_t o[C::NP];
+                E o[C::NP];
                 Planes<C::MODE>::encode(xn, o);
 #pragma unroll
                 for (int p = 0; p < C::NP; ++p) xout[p][k] = o[p];
@@ -249,8 +267,8 @@ __device__ __forceinline__ void lp_epilogue(const uint16_t* __restrict__ Pin, ui
 // iterate X that the FP64 step launched next reads.  Otherwise it returns at
 // once.
 template <class C>
-__global__ __launch_bounds__(C::NT) void k_syrk_lp(const uint16_t* __restrict__ Pin,
-                                                   uint16_t* __restrict__ Pout, size_t pstride,
+__global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __restrict__ Pin,
+                                                   typename C::Elem* __restrict__ Pout, size_t pstride,
                                                    double* __restrict__ X, int ldp, int T, State* st,
                                                    double* __restrict__ part,
                                                    double* __restrict__ scratch,
@@ -272,7 +290,7 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const uint16_t* __restrict__ 
     const int grow = st->grow;
     const unsigned G = gridDim.x;
     const unsigned g = xcd_remap(blockIdx.x, G);
-    const int KT = ldp / kLBK;
+    const int KT = ldp / C::KE;
     const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
     const uint64_t U = (uint64_t)ntiles * KT;
     const uint64_t u0 = U * g / G, u1 = U * (g + 1) / G;
@@ -355,7 +373,8 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const uint16_t* __restrict__ 
 // split-precision phase (at the start of step `step` = m0).
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_f64_to_planes(const double* __restrict__ X,
-                                                            uint16_t* __restrict__ Pout, size_t pstride,
+                                                            typename Planes<MODE>::Elem* __restrict__ Pout,
+                                                            size_t pstride,
                                                             size_t count, const State* st, int step) {
     if (st->done || st->iterations != step || st->phase != 1 || st->lp_steps != 0) return;
     for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < count;
@@ -364,9 +383,11 @@ __global__ __launch_bounds__(kThreads) void k_f64_to_planes(const double* __rest
 }
 
 template <class C>
-static hipError_t launch_lp_cfg(const Layout& L, const uint16_t* Pin, uint16_t* Pout, double* X,
+static hipError_t launch_lp_cfg(const Layout& L, const void* Pin_, void* Pout_, double* X,
                                 State* st, double* part, double* scratch, unsigned* cnt, int step,
                                 hipStream_t s) {
+    const typename C::Elem* Pin = (const typename C::Elem*)Pin_;
+    typename C::Elem* Pout = (typename C::Elem*)Pout_;
     static int per_cu = -1;
     static int cus = 0;
     if (per_cu < 0) {
@@ -396,7 +417,7 @@ static hipError_t launch_lp_cfg(const Layout& L, const uint16_t* Pin, uint16_t* 
 // 8 waves of 64 x 32: two FP64 + one FP32 accumulator sets fit the VGPR budget
 template <int MODE> using LpMain = LpCfg<kLpTile, 2, 4, MODE>;
 
-hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const uint16_t* Pin, uint16_t* Pout,
+hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const void* Pin, void* Pout,
                           double* X, State* st, double* part, double* scratch, unsigned* cnt,
                           int step, hipStream_t s) {
     switch (mode) {
@@ -406,30 +427,28 @@ hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const uint16_t* Pin
             return launch_lp_cfg<LpMain<SP2_C_BF16X3>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
         case SP2_C_BF16X2:
             return launch_lp_cfg<LpMain<SP2_C_BF16X2>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
+        case SP2_C_FP8:
+            return launch_lp_cfg<LpMain<SP2_C_FP8>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
         default:
             return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, uint16_t* Pout,
-                                const State* st, int step, hipStream_t s) {
+template <int MODE>
+static void f64_to_planes_t(const Layout& L, const double* X, void* Pout, const State* st, int step, hipStream_t s) {
     const size_t count = (size_t)L.ldp * L.ldp;
-    const int blocks = 2048;
+    hipLaunchKernelGGL(k_f64_to_planes<MODE>, dim3(2048), dim3(kThreads), 0, s, X,
+                       (typename Planes<MODE>::Elem*)Pout, L.plane_stride, count, st, step);
+}
+
+hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, void* Pout,
+                                const State* st, int step, hipStream_t s) {
     switch (mode) {
-        case SP2_C_F16X2:
-            hipLaunchKernelGGL(k_f64_to_planes<SP2_C_F16X2>, dim3(blocks), dim3(kThreads), 0, s, X, Pout,
-                               L.plane_stride, count, st, step);
-            break;
-        case SP2_C_BF16X3:
-            hipLaunchKernelGGL(k_f64_to_planes<SP2_C_BF16X3>, dim3(blocks), dim3(kThreads), 0, s, X, Pout,
-                               L.plane_stride, count, st, step);
-            break;
-        case SP2_C_BF16X2:
-            hipLaunchKernelGGL(k_f64_to_planes<SP2_C_BF16X2>, dim3(blocks), dim3(kThreads), 0, s, X, Pout,
-                               L.plane_stride, count, st, step);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case SP2_C_F16X2: f64_to_planes_t<SP2_C_F16X2>(L, X, Pout, st, step, s); break;
+        case SP2_C_BF16X3: f64_to_planes_t<SP2_C_BF16X3>(L, X, Pout, st, step, s); break;
+        case SP2_C_BF16X2: f64_to_planes_t<SP2_C_BF16X2>(L, X, Pout, st, step, s); break;
+        case SP2_C_FP8: f64_to_planes_t<SP2_C_FP8>(L, X, Pout, st, step, s); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -129,3 +129,37 @@ def test_mixed_special_cases(sp2):
     D, info = solve(sp2, inst.H, 32, compute="f16x2", fp64_prefix_iters=3, max_iter=6)
     assert info.status == 1 and info.iterations == 6
     assert np.isfinite(D).all() and np.array_equal(D, D.T)
+
+
+def test_fp8_reports_its_floor(sp2, oracle_lib):
+    """Two e4m3 planes (~8 bits): the FP64 prefix and refinement converge, and
+    the subspace error is reported (a BF16X2-class floor, far above 1e-6)."""
+    inst = make_tb_hamiltonian(256, seed=3)
+    D, info = solve(sp2, inst.H, inst.n_occ, compute="fp8")
+    Dj, _, _ = oracle_lib.jacobi_dm(inst.H, inst.n_occ)
+    err = rms(D - Dj)
+    print(f"[gpu] fp8 floor: rms |D - D_jacobi| = {err:.3e}", flush=True)
+    assert info.status in (0, 2)
+    assert info.idempotency < 1e-6
+    assert err <= 1e-2
+
+
+@pytest.mark.parametrize("n", [256, 1028])
+def test_single_fp8_step_entries(sp2, oracle_lib, n):
+    """One FP64 step, then one FP8X2 step, entry by entry: operands carry ~2^-8
+    relative, so the bound is 2^-6 sum_k |x_ik||x_kj| + 1e-6 (an indexing or
+    layout error is O(1))."""
+    inst = make_tb_hamiltonian(n, seed=7)
+    D2, info = solve(sp2, inst.H, inst.n_occ, compute="fp8", fp64_prefix_iters=1, max_iter=2)
+    assert info.status == 1 and info.iterations == 2
+    r1 = oracle_lib.sp2(inst.H, inst.n_occ, max_iter=1)
+    X1 = r1.D
+    grow = int(np.trace(X1) - inst.n_occ <= 0)
+    rng = np.random.default_rng(3)
+    I = np.concatenate([rng.integers(0, n, 3000), np.arange(n)])
+    J = np.concatenate([rng.integers(0, n, 3000), np.arange(n)])
+    want = oracle_lib.sp2_step_entries(X1, grow, I, J)
+    absX = np.abs(X1)
+    bound = 2.0 ** -6 * np.einsum("tk,tk->t", absX[I], absX[J]) + 1e-6
+    assert np.all(np.abs(D2[I, J] - want) <= bound)
+    assert np.array_equal(D2, D2.T)

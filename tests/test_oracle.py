@@ -296,3 +296,61 @@ def test_learned_particle_hole_symmetry(oracle_lib):
     Dm, brm = oracle_lib.learned_matrix(-inst.H, 48 - inst.n_occ, coef)
     assert [1 - b for b in br] == brm
     assert np.abs(Dm - (np.eye(48) - D)).max() < 1e-10
+
+
+# --------------------------------------------------------------------------- Chebyshev expansion
+
+def test_cheb_coeffs_match_library_interpolant(oracle_lib):
+    """The Chebyshev-Gauss coefficients equal NumPy's Chebyshev interpolant of
+    the same function at the same nodes (a wrong node, weight or the factor 2
+    on n > 0 fails)."""
+    from numpy.polynomial import chebyshev as C
+    L, bs, ms = 40, 12.0, 0.1
+    c = oracle_lib.cheb_coeffs(L, bs, ms, q=L + 1)
+    f = lambda x: 1.0 / (1.0 + np.exp(bs * (x - ms)))
+    ref = C.chebinterpolate(f, L)
+    assert np.abs(c - ref).max() < 1e-13
+
+
+def test_cheb_series_converges_to_fermi_function(oracle_lib):
+    from numpy.polynomial import chebyshev as C
+    bs, ms = 30.0, -0.2
+    x = np.linspace(-1, 1, 201)
+    f = 1.0 / (1.0 + np.exp(bs * (x - ms)))
+    errs = [np.abs(C.chebval(x, oracle_lib.cheb_coeffs(L, bs, ms)) - f).max() for L in (20, 60, 200)]
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-9
+
+
+@pytest.mark.parametrize("k,m", [(1, 5), (4, 4), (5, 3), (8, 9)])
+def test_ps_split_reproduces_series(oracle_lib, k, m):
+    """sum_j T_k(x)^j S_j(x) equals the series at random points (a wrong
+    remainder index in the division by T_k fails)."""
+    from numpy.polynomial import chebyshev as C
+    rng = np.random.default_rng(k * 10 + m)
+    c = rng.standard_normal(k * m)
+    d = oracle_lib.cheb_ps_split(c, k, m)
+    x = rng.uniform(-1, 1, 50)
+    Tk = C.chebval(x, np.eye(k + 1)[k])
+    val = np.zeros_like(x)
+    for j in reversed(range(m)):
+        val = C.chebval(x, d[j]) + Tk * val
+    assert np.abs(val - C.chebval(x, c)).max() < 1e-11
+
+
+def test_cheb_density_is_fermi_operator(oracle_lib):
+    """On the matrix: V diag(sum c_n T_n(x_i)) V^T (LAPACK V) equals the serial
+    recursion, and it equals the Fermi operator V diag(f(eps_i)) V^T to the
+    series' own approximation error."""
+    from numpy.polynomial import chebyshev as C
+    inst = make_tb_hamiltonian(64, seed=13, gap=1.0)
+    w, V = np.linalg.eigh(inst.H)
+    mu = 0.5 * (w[31] + w[32])
+    beta = 0.5                                           # 1/eV; ~35 in the scaled variable
+    D, c, (a, b) = oracle_lib.cheb_density(inst.H, 200, beta=beta, mu=mu)
+    lo, hi = oracle_lib.gershgorin(inst.H)
+    assert a == (hi + lo) / 2 and b == (hi - lo) / 2
+    spec = C.chebval((w - a) / b, c)
+    assert np.abs(D - (V * spec) @ V.T).max() < 1e-10
+    fermi = 1.0 / (1.0 + np.exp(beta * (w - mu)))
+    assert np.abs(spec - fermi).max() < 1e-10
+    assert np.abs(D - (V * fermi) @ V.T).max() < 1e-9
