@@ -145,6 +145,26 @@ int sp2_density(const void* H, void* D, int n, int ld, int n_occ, double tol, in
                 size_t workspace_bytes, void* hip_stream, sp2_info* info);
 
 /*
+ * sp2_density without any allocation, for callers that cannot allocate
+ * device or pinned host memory (code that must not call hipMalloc, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments, result
+ * and kernels as sp2_density, but the workspace is a fixed device array of
+ * SP2_NOALLOC_MAX_BYTES bytes inside the library (one per GPU, held until the
+ * process ends), so sp2_workspace_size(n, dtype, compute) must not exceed it
+ * (n <= 1024 for every compute mode); larger problems return
+ * SP2_E_WORKSPACE with D untouched.  The call makes no hipMalloc, hipFree,
+ * hipHostMalloc or event creation: all max_iter steps are queued (steps
+ * after the stop return at once) and the loop state is copied back once into
+ * pageable host memory at the end.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU race, so the caller serialises them.
+ * sp2_history does not apply (the workspace is not the caller's).
+ */
+#define SP2_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int sp2_density_noalloc(const void* H, void* D, int n, int ld, int n_occ, double tol, int max_iter,
+                        sp2_dtype dtype, sp2_compute compute, int fp64_prefix_iters,
+                        void* hip_stream, sp2_info* info);
+
+/*
  * Batched plan (many independent solves in one graph replay).  The paper's
  * graph-partitioned workflow (Section "Graph-based Divide electronic
  * structure") solves one small dense SP2 problem per part, independently;

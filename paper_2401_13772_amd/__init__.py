@@ -53,6 +53,11 @@ _lib.sp2_density.restype = ctypes.c_int
 _lib.sp2_density.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                              ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
                              ctypes.c_size_t, _vp, ctypes.POINTER(sp2_info)]
+_lib.sp2_density_noalloc.restype = ctypes.c_int
+_lib.sp2_density_noalloc.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, _vp, ctypes.POINTER(sp2_info)]
+NOALLOC_MAX_BYTES = 64 << 20
 _lib.sp2_plan_create.restype = ctypes.c_int
 _lib.sp2_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                  ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
@@ -201,6 +206,27 @@ def sp2_density(H, n_occ: int, tol: float = 1e-10, max_iter: int = 100, compute:
     if check and st < 0:
         raise RuntimeError(f"sp2_density failed: {sp2_status_str(st)} ({st})")
     return D, out
+
+
+def sp2_density_noalloc(H, n_occ: int, D, tol: float = 1e-10, max_iter: int = 100,
+                        compute: str = "f64", fp64_prefix_iters: int = -1, stream=None,
+                        n: int = None):
+    """sp2_density with the library's fixed per-GPU workspace (no allocation in
+    the call; sp2_workspace_size(n, ...) must be <= NOALLOC_MAX_BYTES).  D is a
+    preallocated device tensor with H's dtype and leading dimension.
+    Returns (D, Info)."""
+    if H.dim() != 2 or H.stride(1) != 1:
+        raise ValueError("H must be a 2-D row-major device tensor")
+    if n is None:
+        n = H.shape[0]
+    ld = H.stride(0)
+    if D.dtype != H.dtype or D.dim() != 2 or D.stride(1) != 1 or D.stride(0) != ld:
+        raise ValueError("D must have H's dtype and leading dimension, row-major")
+    info = sp2_info()
+    _lib.sp2_density_noalloc(_vp(H.data_ptr()), _vp(D.data_ptr()), int(n), int(ld), int(n_occ),
+                             float(tol), int(max_iter), _dtype_code(H.dtype), COMPUTES[compute],
+                             int(fp64_prefix_iters), _stream_handle(stream), ctypes.byref(info))
+    return D, _info(info)
 
 
 def sp2_history(workspace, count: int = MAX_ITER, stream=None):
@@ -430,7 +456,8 @@ def sp2_profile_read_split():
 
 def exported_symbols():
     """Names of the C entry points this binding wraps."""
-    return ["sp2_version", "sp2_status_str", "sp2_workspace_size", "sp2_density", "sp2_history", "sp2_plan_create", "sp2_plan_run",
+    return ["sp2_version", "sp2_status_str", "sp2_workspace_size", "sp2_density",
+            "sp2_density_noalloc", "sp2_history", "sp2_plan_create", "sp2_plan_run",
             "sp2_plan_config", "sp2_plan_destroy", "sp2_learned_create", "sp2_learned_fit",
             "sp2_learned_coefficients", "sp2_learned_save", "sp2_learned_load", "sp2_learned_density",
             "sp2_learned_destroy", "sp2_cheb_workspace_size", "sp2_cheb_density",
