@@ -23,6 +23,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 OK, NOT_CONVERGED, STAGNATED, INVALID, DEGENERATE = 0, 1, 2, -1, -2
 
 
+class DegenerateError(ValueError):
+    """The zero-temperature density matrix is not unique (vanishing gap)."""
+
+
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP, no FP contraction)."""
     if force or not os.path.exists(_LIB):
@@ -73,6 +77,11 @@ def _load():
                                                 ctypes.c_double, d, ctypes.c_int, d, u64, d]
         lib.oracle_learned_matrix.argtypes = [d, ctypes.c_int, ctypes.c_int, d, ctypes.c_int,
                                               ctypes.c_int, d, u64]
+        ub = ctypes.POINTER(ctypes.c_ubyte)
+        lib.oracle_mu_dm.argtypes = [d, ctypes.c_int, ctypes.c_double, d, d]
+        lib.oracle_graph_parts.argtypes = [d, ctypes.c_int, ctypes.c_double, ctypes.c_int, ub]
+        lib.oracle_graph_density.argtypes = [d, d, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_double, d, i]
         _lib = lib
     return _lib
 
@@ -157,6 +166,8 @@ def jacobi_dm(H, n_occ):
     sw = ctypes.c_int()
     st = _load().oracle_jacobi_dm(_dp(H), n, n_occ, _dp(D), _dp(w), ctypes.byref(gap),
                                   ctypes.byref(sw))
+    if st == DEGENERATE:
+        raise DegenerateError(f"HOMO-LUMO gap {gap.value:.3e} at or below 1e-8 of the spectral width")
     if st != OK:
         raise ValueError(f"oracle_jacobi_dm status {st}")
     return D, w, gap.value
@@ -274,3 +285,57 @@ def cheb_ps_split(c, k, m):
     if st != OK:
         raise ValueError(f"oracle_cheb_ps_split status {st}")
     return d.reshape(m, k)
+
+
+def mu_dm(H, mu):
+    """Zero-temperature D at chemical potential mu: the projector on the
+    eigenvalues below mu (Section "Single-particle density matrix", the
+    Fermi-Dirac function as beta -> infinity).  Returns (D, w)."""
+    H = _f64(H)
+    n = H.shape[0]
+    D = np.empty((n, n))
+    w = np.empty(n)
+    st = _load().oracle_mu_dm(_dp(H), n, float(mu), _dp(D), _dp(w))
+    if st == DEGENERATE:
+        raise DegenerateError(f"an eigenvalue lies within 1e-8 of the spectral width of mu = {mu}")
+    if st != OK:
+        raise ValueError(f"oracle_mu_dm status {st}")
+    return D, w
+
+
+def graph_parts(G, tau, parts):
+    """(parts, n) bool membership of the core-halo parts (Section "Graph-based
+    Divide electronic structure": adjacency |G_lj| >= tau, l != j; core parts
+    = regular segments of the index list; halo = neighbours of core nodes)."""
+    G = _f64(G)
+    n = G.shape[0]
+    out = np.zeros((parts, n), dtype=np.uint8)
+    st = _load().oracle_graph_parts(_dp(G), n, float(tau), int(parts),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    if st != OK:
+        raise ValueError(f"oracle_graph_parts status {st}")
+    return out.astype(bool)
+
+
+def segment_starts(n, parts):
+    """Core part k is [starts[k], starts[k+1]): regular segments of 0..n-1."""
+    return [(k * n) // parts for k in range(parts + 1)]
+
+
+def graph_density(H, tau, parts, mu, G=None):
+    """Graph-partitioned density matrix (the general solver routine of the
+    graph section, with each part's density matrix from Jacobi at chemical
+    potential mu).  G = the auxiliary graph matrix (default H).
+    Returns (D, sizes)."""
+    H = _f64(H)
+    G = H if G is None else _f64(G)
+    n = H.shape[0]
+    D = np.empty((n, n))
+    sizes = np.zeros(parts, dtype=np.int32)
+    st = _load().oracle_graph_density(_dp(H), _dp(G), n, float(tau), int(parts), float(mu), _dp(D),
+                                      _ip(sizes))
+    if st == DEGENERATE:
+        raise DegenerateError("a part has an eigenvalue at mu")
+    if st != OK:
+        raise ValueError(f"oracle_graph_density status {st}")
+    return D, sizes

@@ -48,6 +48,14 @@
  *                        particle-hole form of the same map; with
  *                        (a, b, c) = (1, 0, 0) the two branches are SP2's X^2
  *                        and 2X - X^2).  On eigenvalues and on the matrix.
+ *   oracle_mu_dm, oracle_graph_parts, oracle_graph_density
+ *                        the graph-based divide solver of Section "Graph-based
+ *                        Divide electronic structure": the thresholded
+ *                        adjacency of an auxiliary matrix, core parts as
+ *                        regular segments of the index list, core-halo parts,
+ *                        the dense sub-problem of each part solved at a common
+ *                        chemical potential (zero-temperature Fermi-Dirac, by
+ *                        Jacobi), and the core rows mapped back into D.
  *
  * Readings where the paper is silent (also listed in the design notes):
  *   - H is used through its symmetric part Hs = (H + H^T)/2.
@@ -60,6 +68,11 @@
  *     m >= 2, e_m >= e_{m-2} and e_m < 0.1; otherwise stop at max_iter.
  *   - n_occ == 0 gives D = 0 and n_occ == n gives D = I with no iteration.
  *   - emax == emin with 0 < n_occ < n is degenerate (no unique D).
+ *   - Graph parts: each part's sub-problem is solved at one chemical
+ *     potential mu shared by all parts (a part has no integer electron count
+ *     of its own); only the rows of a part's core nodes are mapped back, so
+ *     every row of D comes from exactly one part and D need not be exactly
+ *     symmetric; the halo is one hop of the thresholded graph.
  *
  * Precision: IEEE double throughout.  Build with -ffp-contract=off so every
  * operation is rounded as written.
@@ -238,7 +251,10 @@ int oracle_jacobi_eigh(const double* A_in, int n, double* w, double* V, int max_
 
 /* D = sum_{i < n_occ} v_i v_i^T from the ascending eigenpairs of H.
  * w (length n) receives the eigenvalues; gap receives w[n_occ] - w[n_occ-1]
- * (0 when n_occ is 0 or n). */
+ * (0 when n_occ is 0 or n).  With 0 < n_occ < n and a gap at or below
+ * 1e-8 (w[n-1] - w[0]) the occupied subspace is not determined by H (the
+ * zero-temperature density matrix is then not unique): D, w and gap are
+ * still written and the status is ORACLE_DEGENERATE. */
 int oracle_jacobi_dm(const double* H, int n, int n_occ, double* D, double* w, double* gap,
                      int* sweeps)
 {
@@ -253,8 +269,10 @@ int oracle_jacobi_dm(const double* H, int n, int n_occ, double* D, double* w, do
             for (int k = 0; k < n_occ; ++k) acc += V[(long)i * n + k] * V[(long)j * n + k];
             D[(long)i * n + j] = acc;
         }
-    if (gap) *gap = (n_occ > 0 && n_occ < n) ? w[n_occ] - w[n_occ - 1] : 0.0;
+    const double g = (n_occ > 0 && n_occ < n) ? w[n_occ] - w[n_occ - 1] : 0.0;
+    if (gap) *gap = g;
     free(V);
+    if (n_occ > 0 && n_occ < n && !(g > 1e-8 * (w[n - 1] - w[0]))) return ORACLE_DEGENERATE;
     return ORACLE_OK;
 }
 
@@ -667,4 +685,108 @@ int oracle_cheb_ps_split(const double* c, int k, int m, double* d)
     }
     free(a); free(qt);
     return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Graph-partitioned density matrix (Section "Graph-based Divide          */
+/* electronic structure": the adjacency equation, core and core-halo      */
+/* partitions, sub-matrix extraction and map-back of the general solver   */
+/* routine listing)                                                         */
+/* ---------------------------------------------------------------------- */
+
+/* Zero-temperature density matrix at a given chemical potential: the
+ * Fermi-Dirac function with beta -> infinity is 1 below mu and 0 above, so
+ * D = sum over the eigenpairs with w_i < mu of v_i v_i^T.  The eigenvalues
+ * go to w.  An eigenvalue within 1e-8 (w[n-1] - w[0]) of mu leaves D
+ * undetermined: D is still written and the status is ORACLE_DEGENERATE. */
+int oracle_mu_dm(const double* H, int n, double mu, double* D, double* w)
+{
+    if (n <= 0 || !H || !D || !w || !isfinite(mu)) return ORACLE_INVALID;
+    double* V = (double*)malloc(sizeof(double) * (size_t)n * n);
+    if (!V) return ORACLE_NOMEM;
+    int st = oracle_jacobi_eigh(H, n, w, V, 100, NULL);
+    if (st != ORACLE_OK) { free(V); return st; }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k)
+                if (w[k] < mu) acc += V[(long)i * n + k] * V[(long)j * n + k];
+            D[(long)i * n + j] = acc;
+        }
+    free(V);
+    const double width = w[n - 1] - w[0];
+    for (int k = 0; k < n; ++k)
+        if (fabs(w[k] - mu) <= 1e-8 * width) return ORACLE_DEGENERATE;
+    return ORACLE_OK;
+}
+
+/* First node of core part k when n nodes are cut into `parts` regular
+ * segments of the index list: floor(k n / parts). */
+static int segment_start(int k, int n, int parts)
+{
+    return (int)(((long)k * n) / parts);
+}
+
+/* Membership of the core-halo parts: in_part[k * n + j] = 1 when node j is
+ * in part k.  Core part k is the k-th regular segment of the index list.
+ * The graph's adjacency is A_lj = 1 when |G_lj| >= tau and l != j; the part
+ * adds to its core every node j with A_lj = 1 for a core node l. */
+int oracle_graph_parts(const double* G, int n, double tau, int parts, unsigned char* in_part)
+{
+    if (!G || !in_part || n <= 0 || parts < 1 || parts > n || !(tau >= 0.0)) return ORACLE_INVALID;
+    for (int k = 0; k < parts; ++k) {
+        unsigned char* row = in_part + (long)k * n;
+        for (int j = 0; j < n; ++j) row[j] = 0;
+        const int c0 = segment_start(k, n, parts), c1 = segment_start(k + 1, n, parts);
+        for (int l = c0; l < c1; ++l) {
+            row[l] = 1;                                   /* the core node */
+            for (int j = 0; j < n; ++j)
+                if (j != l && fabs(G[(long)l * n + j]) >= tau) row[j] = 1;   /* its neighbours */
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* The graph-based density matrix: for every part, the sub-matrix h of H on
+ * the part's nodes (ascending node order), its density matrix at chemical
+ * potential mu (oracle_mu_dm), and the rows of the part's core nodes mapped
+ * back into D (row l of D gets h's row for l, spread over the part's nodes;
+ * every other entry of that row is 0).  sizes[k] = nodes in part k.
+ * Returns ORACLE_DEGENERATE if any part's sub-problem is degenerate. */
+int oracle_graph_density(const double* H, const double* G, int n, double tau, int parts, double mu,
+                         double* D, int* sizes)
+{
+    if (!H || !G || !D || n <= 0 || parts < 1 || parts > n || !(tau >= 0.0) || !isfinite(mu))
+        return ORACLE_INVALID;
+    unsigned char* in_part = (unsigned char*)malloc((size_t)parts * n);
+    int* nodes = (int*)malloc(sizeof(int) * (size_t)n);
+    if (!in_part || !nodes) { free(in_part); free(nodes); return ORACLE_NOMEM; }
+    int st = oracle_graph_parts(G, n, tau, parts, in_part);
+    for (long p = 0; p < (long)n * n; ++p) D[p] = 0.0;
+    int degenerate = 0;
+    for (int k = 0; k < parts && st == ORACLE_OK; ++k) {
+        int s = 0;
+        for (int j = 0; j < n; ++j)
+            if (in_part[(long)k * n + j]) nodes[s++] = j;
+        if (sizes) sizes[k] = s;
+        double* h = (double*)malloc(sizeof(double) * (size_t)s * s);
+        double* d = (double*)malloc(sizeof(double) * (size_t)s * s);
+        double* w = (double*)malloc(sizeof(double) * (size_t)s);
+        if (!h || !d || !w) { free(h); free(d); free(w); st = ORACLE_NOMEM; break; }
+        for (int a = 0; a < s; ++a)
+            for (int b = 0; b < s; ++b) h[(long)a * s + b] = H[(long)nodes[a] * n + nodes[b]];
+        int r = oracle_mu_dm(h, s, mu, d, w);
+        if (r == ORACLE_DEGENERATE) degenerate = 1;
+        else if (r != ORACLE_OK) st = r;
+        const int c0 = segment_start(k, n, parts), c1 = segment_start(k + 1, n, parts);
+        for (int a = 0; a < s; ++a) {
+            const int l = nodes[a];
+            if (l < c0 || l >= c1) continue;              /* halo rows are not kept */
+            for (int b = 0; b < s; ++b) D[(long)l * n + nodes[b]] = d[(long)a * s + b];
+        }
+        free(h); free(d); free(w);
+    }
+    free(in_part); free(nodes);
+    if (st != ORACLE_OK) return st;
+    return degenerate ? ORACLE_DEGENERATE : ORACLE_OK;
 }

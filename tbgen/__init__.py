@@ -157,3 +157,95 @@ def gapped_random_hamiltonian(n: int, n_occ: int, gap: float, seed: int, spread:
     Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
     A = (Q * eps) @ Q.T
     return np.ascontiguousarray(0.5 * (A + A.T)), eps
+
+
+# ---------------------------------------------------------------- local model
+# A tight-binding model whose gap comes from its orbitals rather than from a
+# spectral shift, so that H stays sparse and spatially local (the input of
+# the graph-partitioned solver, which needs locality).
+LOCAL_SPLIT = 8.0        # eV between the two low and the two high orbitals of an atom
+LOCAL_ONSITE_STD = 0.3   # eV
+LOCAL_HOP = 1.5          # eV
+LOCAL_DECAY = 1.0        # Angstrom
+LOCAL_CUTOFF = 5.0       # Angstrom
+LOCAL_MORTON_BITS = 5    # 32^3 cells for the spatial ordering
+
+
+def _morton(c: np.ndarray, bits: int) -> np.ndarray:
+    code = np.zeros(c.shape[0], dtype=np.int64)
+    for b in range(bits):
+        for axis in range(3):
+            code |= ((c[:, axis] >> b) & 1).astype(np.int64) << (3 * b + (2 - axis))
+    return code
+
+
+class LocalInstance:
+    """One local gapped Hamiltonian with the facts of its construction."""
+
+    def __init__(self, H, n_occ, mu, positions, box):
+        self.H = H                  # (n, n) float64 or float32, bitwise symmetric
+        self.n_occ = n_occ          # n / 2: the two low orbitals of every atom
+        self.mu = mu                # 0 eV: the middle of the orbital splitting
+        self.positions = positions  # atoms in index order (Angstrom)
+        self.box = box
+
+    @property
+    def n(self):
+        return self.H.shape[0]
+
+
+def make_local_hamiltonian(n: int, seed: int, dtype=np.float64) -> LocalInstance:
+    """Spatially local, gapped tight-binding Hamiltonian of size ``n``.
+
+    * ``n // 4`` atoms uniform in a periodic cube at density 0.1 / A^3, then
+      ordered along a Morton curve of a 32^3 cell grid (stable), so that
+      regular segments of the index list are compact regions of space;
+    * 4 orbitals per atom: orbitals 0, 1 at -4 eV and 2, 3 at +4 eV, each
+      plus 0.3 N(0, 1) eV;
+    * hopping between orbitals of distinct atoms closer than 5 A (minimum
+      image): ``-1.5 exp(-r / 1 A) s (1 + 0.1 N(0, 1))`` eV with a random
+      sign ``s = +-1`` per orbital pair;
+    * n_occ = n / 2 fills the low orbitals; the gap lies around mu = 0 eV.
+
+    Draw order from ``numpy.random.default_rng(seed)``: positions (natom x 3
+    uniforms); then, over the orbital pairs (i < j) within the cutoff in
+    lexicographic order, one uniform per pair for the sign (s = -1 below
+    1/2), then one normal per pair; then the n onsite normals.
+    """
+    from scipy.spatial import cKDTree
+    if n <= 0 or n % ORBITALS_PER_ATOM:
+        raise ValueError(f"n must be a positive multiple of {ORBITALS_PER_ATOM}, got {n}")
+    natom = n // ORBITALS_PER_ATOM
+    L = box_length(natom)
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, L, size=(natom, 3))
+    g = 1 << LOCAL_MORTON_BITS
+    cell = np.minimum((pos / L * g).astype(np.int64), g - 1)
+    pos = pos[np.argsort(_morton(cell, LOCAL_MORTON_BITS), kind="stable")]
+    pos = np.mod(pos, L)
+    ap = cKDTree(pos, boxsize=L).query_pairs(LOCAL_CUTOFF, output_type="ndarray")
+    ap = ap[np.lexsort((ap[:, 1], ap[:, 0]))] if ap.size else ap.reshape(0, 2)
+    d = pos[ap[:, 0]] - pos[ap[:, 1]]
+    d -= L * np.round(d / L)
+    r = np.sqrt((d * d).sum(axis=1))
+    # every atom pair (a < b) gives the 16 orbital pairs (4a + p, 4b + q)
+    o = np.arange(ORBITALS_PER_ATOM)
+    oi = (ORBITALS_PER_ATOM * ap[:, 0])[:, None, None] + o[None, :, None]
+    oj = (ORBITALS_PER_ATOM * ap[:, 1])[:, None, None] + o[None, None, :]
+    oi, oj = np.broadcast_arrays(oi, oj)
+    oi, oj = oi.reshape(-1), oj.reshape(-1)
+    rr = np.repeat(r, ORBITALS_PER_ATOM * ORBITALS_PER_ATOM)
+    order = np.lexsort((oj, oi))
+    oi, oj, rr = oi[order], oj[order], rr[order]
+    sign = np.where(rng.random(oi.size) < 0.5, -1.0, 1.0)
+    noise = rng.standard_normal(oi.size)
+    onsite = rng.standard_normal(n)
+    hop = -LOCAL_HOP * np.exp(-rr / LOCAL_DECAY) * sign * (1.0 + HOP_NOISE * noise)
+    H = np.zeros((n, n), dtype=np.float64)
+    H[oi, oj] = hop
+    H[oj, oi] = hop
+    orb = np.arange(n) % ORBITALS_PER_ATOM
+    H[np.arange(n), np.arange(n)] = np.where(orb < 2, -LOCAL_SPLIT / 2, LOCAL_SPLIT / 2) + \
+        LOCAL_ONSITE_STD * onsite
+    H = np.ascontiguousarray(H.astype(dtype))
+    return LocalInstance(H, n // 2, 0.0, pos, L)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import golden
-from tbgen import diagonal_hamiltonian, make_tb_hamiltonian, two_level_hamiltonian
+from tbgen import diagonal_hamiltonian, gapped_random_hamiltonian, make_tb_hamiltonian, two_level_hamiltonian
 
 
 def fro_rms(A):
@@ -354,3 +354,103 @@ def test_cheb_density_is_fermi_operator(oracle_lib):
     fermi = 1.0 / (1.0 + np.exp(beta * (w - mu)))
     assert np.abs(spec - fermi).max() < 1e-10
     assert np.abs(D - (V * fermi) @ V.T).max() < 1e-9
+
+
+def test_jacobi_dm_flags_a_vanishing_gap(oracle_lib):
+    """Two equal levels straddling the Fermi level: any unit vector in their
+    span is a valid occupied state, so the oracle reports the case as
+    degenerate rather than returning one of them as the answer; a gap of
+    1e-6 of the width is still resolved."""
+    H = np.diag([-1.0, 0.5, 0.5, 2.0])
+    with pytest.raises(oracle_lib.DegenerateError):
+        oracle_lib.jacobi_dm(H, 2)
+    H2 = np.diag([-1.0, 0.5, 0.5 + 3e-6, 2.0])
+    D, w, gap = oracle_lib.jacobi_dm(H2, 2)
+    assert np.allclose(D, np.diag([1.0, 1.0, 0.0, 0.0]), atol=1e-12) and abs(gap - 3e-6) < 1e-12
+
+
+# ---------------------------------------------------------------- graph solver
+
+def test_graph_parts_hand_worked_chain(oracle_lib):
+    """Core-halo membership of a 6-node graph worked by hand at three
+    thresholds; an asymmetric entry pins that the halo follows row l of the
+    adjacency (node o joins when A_lo = 1 for a core node l)."""
+    g = golden.load("graph_chain6.txt")
+    n, parts = g["n"], int(g["parts"])
+    G = g["G"].reshape(n, n)
+    for key in ("a", "b", "c"):
+        got = oracle_lib.graph_parts(G, g["tau_" + key], parts)
+        want = g["parts_" + key].reshape(parts, n).astype(bool)
+        assert np.array_equal(got, want), key
+
+
+def test_mu_dm_special_cases(oracle_lib):
+    """Diagonal H: D = diag(w < mu); a 2x2 closed form; mu at an eigenvalue
+    is reported degenerate."""
+    H = diagonal_hamiltonian(9, seed=4)
+    D, w = oracle_lib.mu_dm(H, 0.3)
+    assert np.array_equal(np.diag(D), (np.diag(H) < 0.3).astype(float))
+    assert np.abs(D - np.diag(np.diag(D))).max() == 0.0
+    # [[a, c], [c, b]]: occupied eigenvector (cos t, sin t) with tan 2t = 2c/(a-b)
+    a, b, c = 1.0, -0.5, 0.4
+    t = 0.5 * np.arctan2(2 * c, a - b) + np.pi / 2      # the lower eigenvector
+    v = np.array([np.cos(t), np.sin(t)])
+    D2, w2 = oracle_lib.mu_dm(np.array([[a, c], [c, b]]), 0.0)
+    assert np.allclose(D2, np.outer(v, v), atol=1e-14)
+    with pytest.raises(oracle_lib.DegenerateError):
+        oracle_lib.mu_dm(np.diag([-1.0, 0.0, 1.0]), 0.0)
+
+
+def test_graph_density_zero_threshold_is_the_full_solve(oracle_lib):
+    """tau = 0 joins every pair of nodes: every part is the whole matrix and
+    the mapped-back rows assemble the full density matrix."""
+    H, _ = gapped_random_hamiltonian(24, 11, gap=1.0, seed=3)
+    D, sizes = oracle_lib.graph_density(H, 0.0, 4, 0.0)
+    Dfull, _ = oracle_lib.mu_dm(H, 0.0)
+    assert list(sizes) == [24] * 4
+    assert np.abs(D - Dfull).max() < 1e-13
+
+
+def test_graph_density_decoupled_blocks_are_exact(oracle_lib):
+    """H block-diagonal on the core segments: each part is its own block and
+    the result is the exact density matrix; the parts' sizes are the cores."""
+    rng = np.random.default_rng(9)
+    n, parts = 30, 3
+    H = np.zeros((n, n))
+    st = oracle_lib.segment_starts(n, parts)
+    for k in range(parts):
+        m = st[k + 1] - st[k]
+        A = rng.standard_normal((m, m))
+        H[st[k]:st[k + 1], st[k]:st[k + 1]] = A + A.T
+    D, sizes = oracle_lib.graph_density(H, 1e-12, parts, 0.05)
+    Dfull, _ = oracle_lib.mu_dm(H, 0.05)
+    assert list(sizes) == [10, 10, 10]
+    assert np.abs(D - Dfull).max() < 1e-13
+
+
+def test_graph_density_local_model(oracle_lib):
+    """The local gapped model (n = 256): each part's mapped-back rows are the
+    rows of the projector of its sub-matrix (LAPACK), the error against the
+    full projector shrinks as the threshold drops, and the occupation of the
+    assembled D is n/2."""
+    from tbgen import make_local_hamiltonian
+    inst = make_local_hamiltonian(256, seed=2)
+    H, n, parts = inst.H, 256, 4
+    Dfull, _ = oracle_lib.mu_dm(H, inst.mu)
+    errs = []
+    for tau in (0.3, 0.1, 0.03):
+        D, sizes = oracle_lib.graph_density(H, tau, parts, inst.mu)
+        member = oracle_lib.graph_parts(H, tau, parts)
+        assert list(sizes) == list(member.sum(1))
+        st = oracle_lib.segment_starts(n, parts)
+        for k in range(parts):
+            nodes = np.nonzero(member[k])[0]
+            w, V = np.linalg.eigh(H[np.ix_(nodes, nodes)])
+            P = V[:, w < inst.mu] @ V[:, w < inst.mu].T
+            core = np.arange(st[k], st[k + 1])
+            want = np.zeros((core.size, n))
+            want[:, nodes] = P[np.searchsorted(nodes, core)]
+            assert np.abs(D[core] - want).max() < 1e-11
+        errs.append(np.linalg.norm(D - Dfull) / n)
+        assert abs(np.trace(D) - n / 2) < 0.05 * n
+    assert errs[0] > errs[1] > errs[2]
