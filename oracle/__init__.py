@@ -77,6 +77,8 @@ def _load():
                                                 ctypes.c_double, d, ctypes.c_int, d, u64, d]
         lib.oracle_learned_matrix.argtypes = [d, ctypes.c_int, ctypes.c_int, d, ctypes.c_int,
                                               ctypes.c_int, d, u64]
+        lib.oracle_sp2_thresh.argtypes = [d, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_int, d, ctypes.POINTER(_Result), d]
         ub = ctypes.POINTER(ctypes.c_ubyte)
         lib.oracle_mu_dm.argtypes = [d, ctypes.c_int, ctypes.c_double, d, d]
         lib.oracle_graph_parts.argtypes = [d, ctypes.c_int, ctypes.c_double, ctypes.c_int, ub]
@@ -339,3 +341,20 @@ def graph_density(H, tau, parts, mu, G=None):
     if st != OK:
         raise ValueError(f"oracle_graph_density status {st}")
     return D, sizes
+
+
+def sp2_thresh(H, n_occ, tau, tol=1e-10, max_iter=100, nthreads=1):
+    """SP2 with the listing's drop threshold tau (entries with |x| < tau are
+    dropped after the product and after the 2X - X^2 update).  Returns the
+    result of sp2() plus .margin, the closest drop decision
+    (| |v| - tau | / max(|v|, tau))."""
+    H = _f64(H)
+    n = H.shape[0]
+    D = np.zeros((n, n))
+    res = _Result()
+    mg = ctypes.c_double()
+    _load().oracle_sp2_thresh(_dp(H), n, int(n_occ), float(tol), int(max_iter), float(tau),
+                              int(nthreads), _dp(D), ctypes.byref(res), ctypes.byref(mg))
+    out = SP2Result(D, res, np.zeros(0), np.zeros(0))
+    out.margin = mg.value
+    return out

@@ -48,6 +48,10 @@
  *                        particle-hole form of the same map; with
  *                        (a, b, c) = (1, 0, 0) the two branches are SP2's X^2
  *                        and 2X - X^2).  On eigenvalues and on the matrix.
+ *   oracle_sp2_thresh    SP2 with the listing's drop threshold tau: the
+ *                        product and the 2X - X^2 update keep only entries
+ *                        with |x| >= tau (the pruning of the sparse SP2 paths
+ *                        of Section "Leveraging third-party libraries").
  *   oracle_mu_dm, oracle_graph_parts, oracle_graph_density
  *                        the graph-based divide solver of Section "Graph-based
  *                        Divide electronic structure": the thresholded
@@ -68,6 +72,9 @@
  *     m >= 2, e_m >= e_{m-2} and e_m < 0.1; otherwise stop at max_iter.
  *   - n_occ == 0 gives D = 0 and n_occ == n gives D = I with no iteration.
  *   - emax == emin with 0 < n_occ < n is degenerate (no unique D).
+ *   - Thresholded SP2: an entry is dropped when |x| < tau (kept at
+ *     equality), after the product and after 2X - X2; X_0 is kept whole; e
+ *     is measured with the thresholded product.
  *   - Graph parts: each part's sub-problem is solved at one chemical
  *     potential mu shared by all parts (a part has no integer electron count
  *     of its own); only the rows of a part's core nodes are mapped back, so
@@ -789,4 +796,92 @@ int oracle_graph_density(const double* H, const double* G, int n, double tau, in
     free(in_part); free(nodes);
     if (st != ORACLE_OK) return st;
     return degenerate ? ORACLE_DEGENERATE : ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Thresholded SP2 (the drop threshold tau of the SP2 listing: the product */
+/* and the update keep only entries with |x| >= tau, the pruning the       */
+/* sparse solvers of Section "Leveraging third-party libraries" apply)     */
+/* ---------------------------------------------------------------------- */
+
+/* Entry kept by the drop rule; *margin tracks the closest call,
+ * | |v| - tau | / max(|v|, tau), over every decision with tau > 0. */
+static double drop_small(double v, double tau, double* margin)
+{
+    if (tau > 0.0) {
+        double a = fabs(v);
+        double m = fabs(a - tau) / (a > tau ? a : tau);
+        if (m < *margin) *margin = m;
+        if (a < tau) return 0.0;
+    }
+    return v;
+}
+
+/* SP2 as in the listing with a drop threshold: X2 = drop(X X); the update is
+ * X = drop(2 X - X2) or X = X2; X_0 is not thresholded (the listing forms it
+ * by copy, shift and scale).  e_m = ||X2 - X_m||_F with the thresholded X2;
+ * branch, stop rule and special cases as oracle_sp2 (tau = 0 is oracle_sp2).
+ * margin (may be NULL) receives the closest drop decision (see drop_small);
+ * 1 when no decision was taken. */
+int oracle_sp2_thresh(const double* H, int n, int n_occ, double tol, int max_iter, double tau,
+                      int nthreads, double* D, oracle_sp2_result* res, double* margin)
+{
+    if (!res) return ORACLE_INVALID;
+    memset(res, 0, sizeof(*res));
+    double mg = 1.0;
+    if (margin) *margin = 1.0;
+    if (n <= 0 || !H || !D || n_occ < 0 || n_occ > n || !(tol > 0.0) || max_iter < 0 || !(tau >= 0.0)) {
+        res->status = ORACLE_INVALID;
+        return ORACLE_INVALID;
+    }
+    double emin, emax;
+    int st = oracle_gershgorin(H, n, &emin, &emax);
+    if (st != ORACLE_OK) { res->status = st; return st; }
+    res->emin = emin;
+    res->emax = emax;
+    long nn = (long)n * n;
+    if (n_occ == 0 || n_occ == n) {
+        for (long i = 0; i < nn; ++i) D[i] = 0.0;
+        if (n_occ == n)
+            for (int i = 0; i < n; ++i) D[(long)i * n + i] = 1.0;
+        res->trace = (double)n_occ;
+        res->status = ORACLE_OK;
+        return ORACLE_OK;
+    }
+    if (!(emax > emin)) { res->status = ORACLE_DEGENERATE; return ORACLE_DEGENERATE; }
+    double* X = (double*)malloc(sizeof(double) * (size_t)nn);
+    double* S = (double*)malloc(sizeof(double) * (size_t)nn);
+    double* e = (double*)malloc(sizeof(double) * (size_t)(max_iter > 0 ? max_iter : 1));
+    if (!X || !S || !e) { free(X); free(S); free(e); res->status = ORACLE_NOMEM; return ORACLE_NOMEM; }
+    oracle_sp2_init(H, n, emin, emax, X);
+    int status = ORACLE_NOT_CONVERGED;
+    int m;
+    for (m = 0; m < max_iter; ++m) {
+        double tr = trace_of(X, n);
+        square(X, S, n, nthreads);
+        for (long i = 0; i < nn; ++i) S[i] = drop_small(S[i], tau, &mg);
+        double e2 = 0.0;
+        for (long i = 0; i < nn; ++i) {
+            double d = S[i] - X[i];
+            e2 += d * d;
+        }
+        e[m] = sqrt(e2);
+        int grow = (tr - (double)n_occ <= 0.0);
+        if (grow) {
+            for (long i = 0; i < nn; ++i) X[i] = drop_small(2.0 * X[i] - S[i], tau, &mg);
+            if (m < 128) res->branch_mask[m / 64] |= (uint64_t)1 << (m % 64);
+        } else {
+            for (long i = 0; i < nn; ++i) X[i] = S[i];
+        }
+        res->idempotency = e[m];
+        if (e[m] <= tol) { status = ORACLE_OK; ++m; break; }
+        if (m >= 2 && e[m] >= e[m - 2] && e[m] < 0.1) { status = ORACLE_STAGNATED; ++m; break; }
+    }
+    res->iterations = m;
+    res->status = status;
+    memcpy(D, X, sizeof(double) * (size_t)nn);
+    res->trace = trace_of(D, n);
+    if (margin) *margin = mg;
+    free(X); free(S); free(e);
+    return status;
 }

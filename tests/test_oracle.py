@@ -454,3 +454,49 @@ def test_graph_density_local_model(oracle_lib):
         errs.append(np.linalg.norm(D - Dfull) / n)
         assert abs(np.trace(D) - n / 2) < 0.05 * n
     assert errs[0] > errs[1] > errs[2]
+
+
+# ---------------------------------------------------------------- thresholded SP2
+
+def test_sp2_thresh_zero_threshold_is_sp2(oracle_lib):
+    """tau = 0 never drops an entry: the thresholded loop is plain SP2, bit
+    for bit (iterations, branches, D)."""
+    inst = make_tb_hamiltonian(64, seed=12)
+    a = oracle_lib.sp2(inst.H, inst.n_occ)
+    b = oracle_lib.sp2_thresh(inst.H, inst.n_occ, 0.0)
+    assert a.iterations == b.iterations and a.branch_mask == b.branch_mask
+    assert np.array_equal(a.D, b.D) and b.margin == 1.0
+
+
+def test_sp2_thresh_hand_worked_2x2(oracle_lib):
+    """H = [[-1, 0.01], [0.01, 1]], n_occ = 1, tau = 0.01, worked by hand:
+    Gershgorin [-1.01, 1.01], X_0 = (1.01 I - H)/2.02 has trace 1 (a tie:
+    2X - X^2) and off-diagonal -0.01/2.02; the product's off-diagonal
+    x01 (x00 + x11) = -0.01/2.02 is dropped, and so is 2 x01 - 0 =
+    -0.0099 < tau.  X is diagonal from then on and converges to diag(1, 0)
+    (the exact projector has off-diagonal entries of about -0.005)."""
+    H = np.array([[-1.0, 0.01], [0.01, 1.0]])
+    r = oracle_lib.sp2_thresh(H, 1, 0.01)
+    assert r.status == 0 and r.branches()[0] == 1
+    assert np.abs(r.D - np.diag([1.0, 0.0])).max() < 1e-9
+    assert r.D[0, 1] == 0.0 and r.D[1, 0] == 0.0
+    exact = oracle_lib.sp2(H, 1)
+    assert abs(exact.D[0, 1] + 0.005) < 2e-4
+
+
+def test_sp2_thresh_error_follows_tau(oracle_lib):
+    """On the local model the thresholded D approaches plain SP2's as tau
+    falls.  Dropping entries puts a floor of about tau under the idempotency,
+    so with tol = 1e-10 the loop ends by the stagnation rule, at e of order
+    tau; the entries dropped shrink with tau."""
+    from tbgen import make_local_hamiltonian
+    inst = make_local_hamiltonian(128, seed=5)
+    ref = oracle_lib.sp2(inst.H, inst.n_occ)
+    errs, zeros = [], []
+    for tau in (1e-3, 1e-5, 1e-7):
+        r = oracle_lib.sp2_thresh(inst.H, inst.n_occ, tau, nthreads=4)
+        assert r.status == oracle_lib.STAGNATED and r.idempotency < 100 * tau
+        errs.append(np.linalg.norm(r.D - ref.D) / np.sqrt(128))
+        zeros.append(int((r.D == 0).sum()))
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-6
+    assert zeros[0] > zeros[1] > zeros[2]
