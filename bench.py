@@ -127,7 +127,7 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
 
 
-PRODUCTS = {"f64": 1, "f16x2": 3, "bf16x3": 6, "bf16x2": 3}
+PRODUCTS = {"f64": 1, "f16x2": 3, "bf16x3": 6, "bf16x2": 3, "fp8": 3}
 
 
 def timed_solves(sp2, H, D, ws, n_occ, args, compute, steps, warmup, stream):
@@ -165,7 +165,7 @@ def timed_solves(sp2, H, D, ws, n_occ, args, compute, steps, warmup, stream):
 def kernel_lines(kern, n, elapsed, compute):
     flops_per_sq = float(n) * n * (n + 1)
     kinds = {"f64": ("k_syrk_f64", PEAKS_TFLOPS["f64"], 1),
-             "split": ("k_syrk_lp", PEAKS_TFLOPS["f16"], PRODUCTS[compute])}
+             "split": ("k_syrk_lp", PEAKS_TFLOPS["fp8" if compute == "fp8" else "f16"], PRODUCTS[compute])}
     lines = {}
     for key, (ms_tot, launches) in kern.items():
         if launches == 0:
@@ -188,6 +188,266 @@ def kernel_lines(kern, n, elapsed, compute):
             "share_of_solve": round(ms_tot / (1e3 * elapsed), 4),
         }
     return lines
+
+
+def _learned_sample(args):
+    """One generated Hamiltonian of the learned workload: (H, ascending
+    spectrum, Gershgorin bounds, n_occ).  Worker of a process pool."""
+    n, seed, gap, keep_h = args
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from tbgen import make_tb_hamiltonian
+    with threadpool_limits(1):     # one BLAS thread per pool worker
+        inst = make_tb_hamiltonian(n, seed=seed, gap=gap, dtype=np.float32)
+    H = inst.H.astype(np.float64)
+    R = np.abs(H).sum(1) - np.abs(np.diag(H))
+    lo, hi = float((np.diag(H) - R).min()), float((np.diag(H) + R).max())
+    # the spectrum the generator built H from (FP64; the FP32 storage moves
+    # it by ~1e-6 eV, far below what the layers resolve)
+    w = np.sort(inst.eigvals)
+    return (inst.H if keep_h else None), w, (lo, hi), inst.n_occ
+
+
+def bench_learned(args):
+    """The learned recursive expansion: 16 trace-steered quadratic layers
+    trained on the spectra of 20,000 generated n = 512 Hamiltonians (gaps
+    U(0.3, 2) eV, seeds 100000 + s), then inference on 256 held-out ones (seeds
+    200000 + b) against the plain SP2 plan on the same 256.  A step is one
+    solve of the 256; value = density matrices per second of the learned path."""
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+
+    n, L = 512, args.layers
+    rng = np.random.default_rng(args.seed)
+    gaps_tr = rng.uniform(0.3, 2.0, args.train)
+    gaps_te = rng.uniform(0.3, 2.0, args.batch_learned)
+    workers = min(16, len(os.sched_getaffinity(0)))
+    log(f"generating {args.train} training spectra and {args.batch_learned} held-out H (n={n}, {workers} procs)")
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        tr = []
+        for s in pool.imap(_learned_sample, [(n, 100000 + s, float(gaps_tr[s]), False)
+                                             for s in range(args.train)], chunksize=64):
+            tr.append(s)
+            if len(tr) % 2000 == 0:
+                log(f"  {len(tr)} / {args.train} training spectra ({time.perf_counter() - t0:.0f} s)")
+        te = pool.map(_learned_sample, [(n, 200000 + b, float(gaps_te[b]), True)
+                                        for b in range(args.batch_learned)], chunksize=8)
+    log(f"  generated in {time.perf_counter() - t0:.1f} s")
+    import paper_2401_13772_amd as sp2
+    t0 = time.perf_counter()
+    model = sp2.Learned.fit(L, [s[1] for s in tr], [s[3] for s in tr], [s[2] for s in tr],
+                            epochs=args.epochs, seed=args.seed)
+    fit_s = time.perf_counter() - t0
+    coef, loss = model.coefficients()
+    log(f"  trained {L} layers, {args.epochs} epochs in {fit_s:.1f} s, loss {loss:.2f}")
+    Hs = [torch.from_numpy(s[0]).cuda() for s in te]
+    nocc = [s[3] for s in te]
+    Ds = [torch.empty_like(H) for H in Hs]
+    for _ in range(args.warmup):
+        model.density(Hs, nocc, Ds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, infos = model.density(Hs, nocc, Ds)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    plan = sp2.Plan([n] * len(Hs), nocc, dtype="f32", tol=1e-10, max_iter=60)
+    D2 = [torch.empty_like(H) for H in Hs]
+    plan.run(Hs, D2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, pinfos = plan.run(Hs, D2)
+    torch.cuda.synchronize()
+    el2 = (time.perf_counter() - t0) / args.steps
+    errs = []
+    for k, s in enumerate(te):
+        w, V = np.linalg.eigh(s[0].astype(np.float64))
+        Dref = V[:, :s[3]] @ V[:, :s[3]].T
+        errs.append(float(np.linalg.norm(Ds[k].cpu().numpy().astype(np.float64) - Dref)) / np.sqrt(n))
+    errs = np.array(errs)
+    st = np.array([i.status for i in infos])
+    layers_its = np.array([i.iterations for i in infos])
+    sp2_its = np.array([i.iterations for i in pinfos])
+    flops = sum(float(n) * n * (n + 1) * i.iterations for i in infos)
+    out = {
+        "metric": METRIC, "value": round(len(Hs) / el, 2), "unit": "DM/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * el, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"sp2_learned{L}_n512_batch{len(Hs)}_f32storage", "layers": L, "train": args.train,
+                   "epochs": args.epochs},
+        "fit_seconds": round(fit_s, 2), "fit_loss": loss,
+        "plain_sp2_plan": {"value": round(len(Hs) / el2, 2), "unit": "DM/s", "mean_iterations": float(sp2_its.mean())},
+        "speedup_vs_plain_sp2": round(el2 / el, 3),
+        "mean_squarings": float(layers_its.mean()),
+        "status_counts": {"ok": int((st == 0).sum()), "fallback": int((st == 3).sum()),
+                          "other": int(((st != 0) & (st != 3)).sum())},
+        "err_rms_vs_eigh": {"median": float(np.median(errs)), "max": float(errs.max())},
+        "meets_1e-6": bool(errs.max() <= 1e-6),
+        "tflops_algorithmic": round(flops / el / 1e12, 3),
+        "roofline": {"bound": "mfma", "achieved": round(flops / el / 1e12, 3), "peak": PEAKS_TFLOPS["f64"],
+                     "unit": "TFLOP/s", "frac": round(flops / el / 1e12 / PEAKS_TFLOPS["f64"], 4),
+                     "traffic": None,
+                     "note": "whole batched learned solve (all kernels) against the FP64 matrix peak"},
+        "coefficients": coef.tolist(),
+    }
+    model.close()
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_graph(args):
+    """The graph-partitioned solver on the local gapped model: n = 16384 (4096
+    atoms), 64 core parts of 256 orbitals, threshold 0.03 eV on H, FP32
+    storage, FP64 squarings, mu = 0 (mid-gap by construction).  A step is one
+    sp2_graph_density call (gather, batched mu-steered SP2 of the 64 parts,
+    map-back); value = full density matrices per second.  The dense FP64 SP2
+    solve of the same H is timed beside it and is the error reference."""
+    import numpy as np
+    import torch
+
+    import paper_2401_13772_amd as sp2
+    from tbgen import make_local_hamiltonian
+    n, parts, tau = args.graph_n, args.graph_parts, args.graph_tau
+    log(f"generating the local gapped model n={n}")
+    t0 = time.perf_counter()
+    inst = make_local_hamiltonian(n, seed=args.seed, dtype=np.float32)
+    log(f"  generated in {time.perf_counter() - t0:.1f} s")
+    H = torch.from_numpy(inst.H).cuda()
+    del inst.H
+    t0 = time.perf_counter()
+    g = sp2.Graph(H, tau, parts, tol=args.tol)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    sizes, cores = g.sizes()
+    log(f"  {parts} parts, core {min(cores)}..{max(cores)}, core+halo {min(sizes)}..{max(sizes)} "
+        f"(created in {create_s:.2f} s)")
+    D = torch.empty_like(H)
+    for _ in range(args.warmup):
+        g.density(H, inst.mu, D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, infos = g.density(H, inst.mu, D)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    bad = [(k, i.status_str, i.iterations, i.idempotency) for k, i in enumerate(infos) if i.status != 0]
+    assert not bad, f"parts that did not converge: {bad[:4]}"
+    flops = sum(float(s) * s * (s + 1) * i.iterations for s, i in zip(sizes, infos))
+    log(f"  graph solve {1e3 * el:.2f} ms, {flops / el / 1e12:.2f} TFLOP/s algorithmic")
+    # dense FP64 SP2 of the same H (one warm-up, then timed)
+    ws = sp2.alloc_workspace(n, "f32", "f64")
+    Dd = torch.empty_like(H)
+    sp2.sp2_density(H, n // 2, tol=args.tol, D=Dd, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dense_steps = max(1, min(args.steps, 2))
+    for _ in range(dense_steps):
+        _, idense = sp2.sp2_density(H, n // 2, tol=args.tol, D=Dd, workspace=ws)
+    torch.cuda.synchronize()
+    el_dense = (time.perf_counter() - t0) / dense_steps
+    del ws
+    diff = (D.double() - Dd.double())
+    err = float(torch.linalg.norm(diff)) / np.sqrt(n)
+    err_avg = float(torch.linalg.norm(diff)) / n
+    asym = float(torch.linalg.norm(D.double() - D.double().T)) / np.sqrt(n)
+    tr_err = abs(float(torch.trace(D.double())) - n / 2)
+    log(f"  dense FP64 SP2 {1e3 * el_dense:.1f} ms ({idense.iterations} squarings); "
+        f"rms|D_graph - D_dense| = {err:.3e}, ||.||_F/n = {err_avg:.3e}, trace error {tr_err:.3e}")
+    tf = flops / el / 1e12
+    out = {
+        "metric": METRIC, "value": round(1.0 / el, 4), "unit": "DM/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * el, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"sp2_graph_local_n{n}_parts{parts}_tau{tau:g}_f32storage_f64", "n": n,
+                   "parts": parts, "tau_eV": tau, "mu_eV": inst.mu, "tol": args.tol},
+        "parts": {"core_min": min(cores), "core_max": max(cores), "size_min": min(sizes),
+                  "size_max": max(sizes), "size_mean": round(float(np.mean(sizes)), 1),
+                  "iterations_max": max(i.iterations for i in infos), "create_s": round(create_s, 3)},
+        "dense_fp64_sp2": {"value": round(1.0 / el_dense, 4), "unit": "DM/s", "ms": round(1e3 * el_dense, 2),
+                           "iterations": idense.iterations},
+        "speedup_vs_dense_fp64": round(el_dense / el, 2),
+        "err_rms_vs_dense": err, "err_fro_over_n_vs_dense": err_avg, "asymmetry_rms": asym,
+        "trace_error": tr_err,
+        "tflops_algorithmic": round(tf, 3),
+        "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAKS_TFLOPS["f64"], "unit": "TFLOP/s",
+                     "frac": round(tf / PEAKS_TFLOPS["f64"], 4), "traffic": None,
+                     "note": "whole graph solve (gather, batched steps, map-back) against the FP64 matrix peak"},
+    }
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_sparse(args):
+    """Thresholded SP2 with tile skipping on the local gapped model: n = 16384,
+    tau = 1e-5, FP32 storage, FP64 arithmetic.  A step is one
+    sp2_density_sparse solve; the dense FP64 SP2 of the same H is timed beside
+    it and is the error reference."""
+    import numpy as np
+    import torch
+
+    import paper_2401_13772_amd as sp2
+    from tbgen import make_local_hamiltonian
+    n, tau = args.sparse_n, args.sparse_tau
+    log(f"generating the local gapped model n={n}")
+    inst = make_local_hamiltonian(n, seed=args.seed, dtype=np.float32)
+    H = torch.from_numpy(inst.H).cuda()
+    del inst.H
+    nbytes = sp2.sp2_sparse_workspace_size(n)
+    wraw = torch.empty(nbytes + sp2.WORKSPACE_ALIGN, dtype=torch.uint8, device="cuda")
+    off = (-wraw.data_ptr()) % sp2.WORKSPACE_ALIGN
+    ws = wraw[off:off + nbytes]
+    D = torch.empty_like(H)
+    for _ in range(args.warmup):
+        sp2.sp2_density_sparse(H, inst.n_occ, tau, tol=args.tol, D=D, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, info = sp2.sp2_density_sparse(H, inst.n_occ, tau, tol=args.tol, D=D, workspace=ws)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    flops_exec, tile_steps = sp2.sp2_sparse_stats(ws)
+    T = (n + 127) // 128
+    dense_eq = float(n) * n * (n + 1) * info.iterations
+    log(f"  sparse solve {1e3 * el:.1f} ms, {info.iterations} steps, status {info.status_str}, "
+        f"executed {flops_exec / dense_eq:.3f} of the dense work, {flops_exec / el / 1e12:.2f} TFLOP/s executed")
+    del ws, wraw
+    wsd = sp2.alloc_workspace(n, "f32", "f64")
+    Dd = torch.empty_like(H)
+    sp2.sp2_density(H, inst.n_occ, tol=1e-10, D=Dd, workspace=wsd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, idense = sp2.sp2_density(H, inst.n_occ, tol=1e-10, D=Dd, workspace=wsd)
+    torch.cuda.synchronize()
+    el_dense = time.perf_counter() - t0
+    del wsd
+    diff = D.double() - Dd.double()
+    err = float(torch.linalg.norm(diff)) / np.sqrt(n)
+    zero_frac = float((D == 0).double().mean())
+    log(f"  dense FP64 SP2 {1e3 * el_dense:.1f} ms; rms|D_sparse - D_dense| = {err:.3e}; "
+        f"zero entries {zero_frac:.3f}")
+    tf = flops_exec / el / 1e12
+    out = {
+        "metric": METRIC, "value": round(1.0 / el, 4), "unit": "DM/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * el, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"sp2_sparse_local_n{n}_tau{tau:g}_f32storage_f64", "n": n, "tau": tau,
+                   "tol": args.tol},
+        "status": info.status_str, "iterations": info.iterations, "idempotency": info.idempotency,
+        "trace_error": info.trace_error,
+        "executed_fraction_of_dense": round(flops_exec / dense_eq, 4),
+        "tile_fraction": round(tile_steps / (info.iterations * T * (T + 1) / 2), 4),
+        "dense_fp64_sp2": {"value": round(1.0 / el_dense, 4), "unit": "DM/s", "ms": round(1e3 * el_dense, 2),
+                           "iterations": idense.iterations},
+        "speedup_vs_dense_fp64": round(el_dense / el, 3),
+        "err_rms_vs_dense": err, "zero_entry_fraction": round(zero_frac, 4),
+        "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAKS_TFLOPS["f64"], "unit": "TFLOP/s",
+                     "frac": round(tf / PEAKS_TFLOPS["f64"], 4), "traffic": None,
+                     "note": "executed FP64 MFMA work of the tile-skipping solve over its wall time"},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args):
@@ -269,7 +529,7 @@ def main():
     ap.add_argument("--gap", type=float, default=0.5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--compute", default="f16x2", choices=["f64", "f16x2", "bf16x3", "bf16x2"])
+    ap.add_argument("--compute", default="f16x2", choices=["f64", "f16x2", "bf16x3", "bf16x2", "fp8"])
     ap.add_argument("--prefix", type=int, default=-1,
                     help="FP64 steps before the split-operand phase (-1 = library default)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
@@ -279,9 +539,18 @@ def main():
                     help="oracle squarings in the CPU-baseline sample (0 = skip)")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 eigendecomposition accuracy check (profiling runs)")
-    ap.add_argument("--workload", default="single", choices=["single", "batch"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "learned", "graph", "sparse"],
                     help="single: one n x n solve (default); batch: the batched plan (512 problems)")
     ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--graph-n", type=int, default=16384, help="graph workload: matrix size")
+    ap.add_argument("--graph-parts", type=int, default=64, help="graph workload: core parts")
+    ap.add_argument("--graph-tau", type=float, default=0.03, help="graph workload: adjacency threshold (eV)")
+    ap.add_argument("--sparse-n", type=int, default=16384, help="sparse workload: matrix size")
+    ap.add_argument("--sparse-tau", type=float, default=1e-5, help="sparse workload: drop threshold")
+    ap.add_argument("--layers", type=int, default=16, help="learned workload: quadratic layers")
+    ap.add_argument("--train", type=int, default=20000, help="learned workload: training Hamiltonians")
+    ap.add_argument("--epochs", type=int, default=60, help="learned workload: passes over the training set")
+    ap.add_argument("--batch-learned", type=int, default=256, help="learned workload: held-out batch")
     ap.add_argument("--batch-max-iter", type=int, default=60)
     ap.add_argument("--autotune-cache", default="",
                     help="batch: autotune the tile shape with this cache file (default: no autotune)")
@@ -304,6 +573,15 @@ def main():
 
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
+        return
+    if args.workload == "graph":
+        bench_graph(args)
+        return
+    if args.workload == "sparse":
+        bench_sparse(args)
         return
 
     import paper_2401_13772_amd as sp2
@@ -356,7 +634,7 @@ def main():
     peak_time = 0.0
     for key, (ms_tot, launches) in kern.items():
         if launches:
-            peak = PEAKS_TFLOPS["f64"] if key == "f64" else PEAKS_TFLOPS["f16"]
+            peak = PEAKS_TFLOPS["f64"] if key == "f64" else PEAKS_TFLOPS["fp8" if args.compute == "fp8" else "f16"]
             mult = 1 if key == "f64" else PRODUCTS[args.compute]
             peak_time += launches * flops_per_sq * mult / (peak * 1e12)
     solve_frac = peak_time / elapsed

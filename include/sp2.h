@@ -133,7 +133,10 @@ size_t sp2_workspace_size(int n, sp2_dtype dtype, sp2_compute compute);
  *                    (not steered by the trace) until e <= tol, at most 8.
  *               info->fp64_prefix_iters and info->refine_steps report 1 and 3.
  *   fp64_prefix_iters  steps of phase 1 for the split modes: -1 = automatic
- *               (12), otherwise 1..SP2_MAX_ITER; ignored for SP2_C_F64.
+ *               (F16X2: 8, BF16X3: 6, others 8; two more for n > 4096,
+ *               calibrated on MI355X to keep rms |D - D_ref| <= 7e-7 for gaps
+ *               >= 0.3 eV on a ~140 eV spectral interval), otherwise
+ *               1..SP2_MAX_ITER; ignored for SP2_C_F64.
  *   workspace   device buffer of at least sp2_workspace_size(n, dtype,
  *               compute) bytes, aligned to SP2_WORKSPACE_ALIGN.
  *   hip_stream  hipStream_t or NULL.
@@ -200,6 +203,89 @@ int sp2_plan_run(sp2_plan* plan, const void* const* H, void* const* D, void* hip
                  sp2_info* infos);
 const char* sp2_plan_config(const sp2_plan* plan);
 int sp2_plan_destroy(sp2_plan* plan);
+
+/*
+ * Thresholded SP2 with tile skipping.  The SP2 listing (Section "SP2 solver")
+ * passes a cutoff tau to its multiply and add; the sparse solvers of Section
+ * "Leveraging third-party libraries" prune the entries below it.  Here:
+ * X2 = drop(X X) and X <- drop(2X - X2) or X2, where drop zeroes every entry
+ * with |x| < tau; X_0 is formed whole; e_m = ||X2 - X_m||_F; steering, stop
+ * rule and special cases as sp2_density (FP64 throughout).  Dropping puts a
+ * floor of about tau under e, so a solve with tol below it ends by the
+ * stagnation rule (SP2_E_STAGNATED, D is the last iterate).  Storage is
+ * dense; a 128 x 128 tile of a product is computed only over the K tiles
+ * where both operand tiles hold a nonzero, and an all-zero tile of the
+ * iterate is skipped, so a spatially local H (sorted so that near orbitals
+ * have near indices) costs far fewer than n^3 operations per step.
+ *   H, D, n, ld, n_occ, tol, max_iter, dtype, hip_stream, info: as
+ *               sp2_density; n <= 65536.
+ *   tau         drop threshold, >= 0 (0: plain FP64 SP2 with tile skipping).
+ *   workspace   at least sp2_sparse_workspace_size(n) bytes, aligned to
+ *               SP2_WORKSPACE_ALIGN: the loop state, partial sums, two tile
+ *               maps and two FP64 iterates padded to a multiple of 128.
+ *               sp2_history reads the trace and e histories from it.
+ */
+size_t sp2_sparse_workspace_size(int n);
+/* After a solve on this workspace (and after the stream has reached it):
+ * the multiply-add work the tile skipping left, as flops (2 per multiply-add,
+ * the lower tiles only), and the number of (step, lower tile) pairs computed. */
+int sp2_sparse_stats(const void* workspace, void* hip_stream, double* executed_flops, double* tile_steps);
+int sp2_density_sparse(const void* H, void* D, int n, int ld, int n_occ, double tol, int max_iter,
+                       sp2_dtype dtype, double tau, void* workspace, size_t workspace_bytes,
+                       void* hip_stream, sp2_info* info);
+
+/*
+ * Graph-partitioned solver (Section "Graph-based Divide electronic
+ * structure": the adjacency equation, core and core-halo partitions, the
+ * extraction of sub-matrices and the map-back of the general solver routine
+ * listing).  The graph of an auxiliary matrix G (H itself, an overlap matrix
+ * or an earlier density matrix) joins nodes l != o with |G_lo| >= tau.  Core
+ * part k is the k-th of `parts` regular segments of the index list,
+ * [floor(k n / parts), floor((k + 1) n / parts)); its core-halo part adds
+ * every node o with |G_lo| >= tau for a core node l (row l of G).  A solve
+ * takes the dense sub-matrix of H on each core-halo part (nodes in
+ * ascending order), solves all of them as one batched plan at a common
+ * chemical potential mu, and writes row l of D, for each core node l, from
+ * its part: the part's row spread over the part's nodes, 0 in every other
+ * column.  Each part's SP2 steps are steered by mu instead of an occupation:
+ * with x_mu = (emax - mu)/(emax - emin) the image of mu under X_0 (the
+ * part's Gershgorin bounds), a step takes X^2 when x_mu > 1/2 and 2X - X^2
+ * otherwise, and x_mu follows the same map; eigenvalues below mu go to 1 and
+ * those above to 0, so each part converges to the projector on its
+ * eigenvalues below mu (the zero-temperature Fermi-Dirac function of Section
+ * "Single-particle density matrix").  mu at or below emin gives 0, at or
+ * above emax the identity, with no step.  Stop rule as in sp2_density,
+ * except that the stagnation test compares e_m with e_{m-3} and waits for
+ * e < 1e-3 (mu's image takes at most two equal branches in a row, during
+ * which levels on one side may move away from 0 or 1).
+ *
+ * sp2_graph_create: G is a device pointer, n x n row-major with leading
+ *   dimension ld, storage dtype; 1 <= n <= 65536, 1 <= parts <= min(n, 4096),
+ *   tau >= 0.  Builds the parts on the current device (reads G once, one host
+ *   synchronisation on hip_stream), allocates the parts' buffers and
+ *   captures the batched plan (tol, max_iter as in sp2_density).  A part with
+ *   more than SP2_PLAN_MAX_N nodes returns SP2_E_UNSUPPORTED.
+ * sp2_graph_parts: writes the node count and the core node count of every
+ *   part (host arrays of `parts` ints, each may be NULL); returns parts.
+ * sp2_graph_nodes: copies part `part`'s ascending node list into a host
+ *   array of capacity ints; returns the part's size (nothing is copied when
+ *   nodes is NULL or capacity is short).
+ * sp2_graph_density: H, D device pointers, n x n, leading dimension ld,
+ *   storage dtype, no overlap.  Returns after D is written; infos (host
+ *   array of `parts` records, may be NULL) gets each part's solve record
+ *   (trace = the part's occupation, trace_error 0).  Returns the most
+ *   negative per-part status if any is negative (D is then unspecified),
+ *   else the largest.  Calls on one graph must not overlap.
+ * sp2_graph_destroy: frees the graph and its plan.
+ */
+typedef struct sp2_graph sp2_graph;
+int sp2_graph_create(sp2_graph** graph, const void* G, int n, int ld, sp2_dtype dtype, double tau,
+                     int parts, double tol, int max_iter, void* hip_stream);
+int sp2_graph_parts(const sp2_graph* graph, int* sizes, int* core_sizes);
+int sp2_graph_nodes(const sp2_graph* graph, int part, int* nodes, int capacity);
+int sp2_graph_density(sp2_graph* graph, const void* H, void* D, int ld, sp2_dtype dtype, double mu,
+                      void* hip_stream, sp2_info* infos);
+int sp2_graph_destroy(sp2_graph* graph);
 
 /*
  * Learned recursive expansion: a composition of trained quadratic maps of the

@@ -72,6 +72,26 @@ PLAN_MAX_N = 2048
 _lib.sp2_cheb_workspace_size.restype = ctypes.c_size_t
 _lib.sp2_cheb_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int]
 _lib.sp2_cheb_density.restype = ctypes.c_int
+_lib.sp2_sparse_workspace_size.restype = ctypes.c_size_t
+_lib.sp2_sparse_workspace_size.argtypes = [ctypes.c_int]
+_lib.sp2_sparse_stats.restype = ctypes.c_int
+_lib.sp2_sparse_stats.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.sp2_density_sparse.restype = ctypes.c_int
+_lib.sp2_density_sparse.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, ctypes.c_size_t, _vp,
+                                    ctypes.POINTER(sp2_info)]
+_lib.sp2_graph_create.restype = ctypes.c_int
+_lib.sp2_graph_create.argtypes = [ctypes.POINTER(_vp), _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int, _vp]
+_lib.sp2_graph_parts.restype = ctypes.c_int
+_lib.sp2_graph_parts.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.sp2_graph_nodes.restype = ctypes.c_int
+_lib.sp2_graph_nodes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+_lib.sp2_graph_density.restype = ctypes.c_int
+_lib.sp2_graph_density.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp,
+                                   ctypes.POINTER(sp2_info)]
+_lib.sp2_graph_destroy.restype = ctypes.c_int
+_lib.sp2_graph_destroy.argtypes = [_vp]
 _lib.sp2_cheb_density.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp,
                                   ctypes.POINTER(sp2_info)]
@@ -271,6 +291,114 @@ def sp2_cheb_density(H, mu: float, beta: float, k: int, m: int, D=None, workspac
     return D, _info(info)
 
 
+def sp2_sparse_workspace_size(n: int) -> int:
+    return int(_lib.sp2_sparse_workspace_size(int(n)))
+
+
+def sp2_density_sparse(H, n_occ: int, tau: float, tol: float = 1e-10, max_iter: int = 100, D=None,
+                       workspace=None, stream=None):
+    """Thresholded SP2 with tile skipping (sp2_density_sparse).  Returns (D, Info)."""
+    import torch
+    if H.dim() != 2 or H.shape[0] != H.shape[1] or H.stride(1) != 1:
+        raise ValueError("H must be a square row-major device tensor")
+    n = H.shape[0]
+    ld = H.stride(0)
+    if D is None:
+        D = torch.empty((n, ld), dtype=H.dtype, device=H.device)[:, :n]
+    if D.dtype != H.dtype or D.stride(0) != ld or D.stride(1) != 1:
+        raise ValueError("D must have H's dtype and leading dimension, row-major")
+    nbytes = sp2_sparse_workspace_size(n)
+    if nbytes == 0:
+        raise ValueError("invalid size")
+    if workspace is None:
+        ws = torch.empty(nbytes + WORKSPACE_ALIGN, dtype=torch.uint8, device=H.device)
+        off = (-ws.data_ptr()) % WORKSPACE_ALIGN
+        workspace = ws[off:off + nbytes]
+    info = sp2_info()
+    _lib.sp2_density_sparse(_vp(H.data_ptr()), _vp(D.data_ptr()), int(n), int(ld), int(n_occ), float(tol),
+                            int(max_iter), _dtype_code(H.dtype), float(tau), _vp(workspace.data_ptr()),
+                            int(workspace.numel()), _stream_handle(stream), ctypes.byref(info))
+    return D, _info(info)
+
+
+def sp2_sparse_stats(workspace, stream=None):
+    """(executed flops, computed (step, tile) pairs) of the last sparse solve on workspace."""
+    f = ctypes.c_double()
+    t = ctypes.c_double()
+    st = _lib.sp2_sparse_stats(_vp(workspace.data_ptr()), _stream_handle(stream), ctypes.byref(f), ctypes.byref(t))
+    if st != OK:
+        raise RuntimeError(f"sp2_sparse_stats failed: {sp2_status_str(st)}")
+    return f.value, t.value
+
+
+class Graph:
+    """A graph-partitioned solver (sp2_graph_create): core-halo parts of the
+    thresholded graph of G, solved together at a chemical potential by
+    density()."""
+
+    def __init__(self, G, tau: float, parts: int, tol: float = 1e-10, max_iter: int = 100, stream=None):
+        if G.dim() != 2 or G.shape[0] != G.shape[1] or G.stride(1) != 1:
+            raise ValueError("G must be a square row-major device tensor")
+        self.n = int(G.shape[0])
+        self._h = _vp()
+        st = _lib.sp2_graph_create(ctypes.byref(self._h), _vp(G.data_ptr()), self.n, int(G.stride(0)),
+                                   _dtype_code(G.dtype), float(tau), int(parts), float(tol), int(max_iter),
+                                   _stream_handle(stream))
+        if st != OK:
+            self._h = _vp()
+            raise RuntimeError(f"sp2_graph_create failed: {sp2_status_str(st)} ({st})")
+        self.parts = int(parts)
+
+    def sizes(self):
+        """(nodes per part, core nodes per part) as lists."""
+        a = (ctypes.c_int * self.parts)()
+        c = (ctypes.c_int * self.parts)()
+        _lib.sp2_graph_parts(self._h, a, c)
+        return list(a), list(c)
+
+    def nodes(self, part: int):
+        """Ascending node list of one part."""
+        s = _lib.sp2_graph_nodes(self._h, int(part), None, 0)
+        if s < 0:
+            raise ValueError("no such part")
+        buf = (ctypes.c_int * s)()
+        st = _lib.sp2_graph_nodes(self._h, int(part), buf, s)
+        if st != s:
+            raise RuntimeError(f"sp2_graph_nodes failed: {st}")
+        return list(buf)
+
+    def density(self, H, mu: float, D=None, stream=None):
+        """D of H at chemical potential mu; returns (D, [Info per part])."""
+        import torch
+        if not self._h:
+            raise RuntimeError("graph is closed")
+        if H.dim() != 2 or tuple(H.shape) != (self.n, self.n) or H.stride(1) != 1:
+            raise ValueError("H must be an (n, n) row-major device tensor")
+        ld = H.stride(0)
+        if D is None:
+            D = torch.empty((self.n, ld), dtype=H.dtype, device=H.device)[:, :self.n]
+        if D.dtype != H.dtype or D.stride(0) != ld or D.stride(1) != 1:
+            raise ValueError("D must have H's dtype and leading dimension, row-major")
+        infos = (sp2_info * self.parts)()
+        st = _lib.sp2_graph_density(self._h, _vp(H.data_ptr()), _vp(D.data_ptr()), int(ld),
+                                    _dtype_code(H.dtype), float(mu), _stream_handle(stream), infos)
+        self.last_status = int(st)
+        if st in (E_HIP, E_INVALID):
+            raise RuntimeError(f"sp2_graph_density failed: {sp2_status_str(st)} ({st})")
+        return D, [_info(i) for i in infos]
+
+    def close(self):
+        if self._h:
+            _lib.sp2_graph_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """A batched plan (sp2_plan_create): `sizes[b]` x `sizes[b]` problems with
     occupations n_occ[b], solved together by run() in one graph replay."""
@@ -461,4 +589,6 @@ def exported_symbols():
             "sp2_plan_config", "sp2_plan_destroy", "sp2_learned_create", "sp2_learned_fit",
             "sp2_learned_coefficients", "sp2_learned_save", "sp2_learned_load", "sp2_learned_density",
             "sp2_learned_destroy", "sp2_cheb_workspace_size", "sp2_cheb_density",
+            "sp2_graph_create", "sp2_graph_parts", "sp2_graph_nodes", "sp2_graph_density",
+            "sp2_graph_destroy", "sp2_sparse_workspace_size", "sp2_density_sparse", "sp2_sparse_stats",
             "sp2_profile_enable", "sp2_profile_read", "sp2_profile_read_split"]

@@ -9,25 +9,37 @@
 
 namespace sp2 {
 
+// LDS tile type of storage type T (FP32 storage: FP32 tiles).
+template <typename T>
+struct PairLds {
+    typedef double type;
+};
+template <>
+struct PairLds<float> {
+    typedef float type;
+};
+
 // The lower tile pairs: block p handles tiles (I, J) and (J, I), I >= J
 // (tri_tile numbering), so every element of H is read once.  The symmetric
 // part Hs_ij = (H_ij + H_ji)/2 of the pair is formed from the two tiles in
 // LDS.
 
 // Loads tiles (I, J) -> sA and (J, I) -> sB (zero outside n x n) and reports
-// a non-finite entry.
-template <typename T>
+// a non-finite entry.  L, the LDS element type, is the storage type (FP32
+// storage keeps FP32 tiles: half the LDS, twice the workgroups per CU, the
+// same values once widened).
+template <typename T, typename L>
 __device__ inline void load_pair(const T* __restrict__ H, int n, int ld, int I, int J,
-                                 double (*sA)[kBndTile + 1], double (*sB)[kBndTile + 1], int& bad) {
+                                 L (*sA)[kBndTile + 1], L (*sB)[kBndTile + 1], int& bad) {
     for (int e = threadIdx.x; e < kBndTile * kBndTile; e += kThreads) {
         const int rr = e >> 6, cc = e & 63;
         const int ra = I * kBndTile + rr, ca = J * kBndTile + cc;
         const int rb = J * kBndTile + rr, cb = I * kBndTile + cc;
-        const double a = (ra < n && ca < n) ? (double)H[(size_t)ra * ld + ca] : 0.0;
-        const double b = (rb < n && cb < n) ? (double)H[(size_t)rb * ld + cb] : 0.0;
-        bad |= !isfinite(a) | !isfinite(b);
-        sA[rr][cc] = a;
-        sB[rr][cc] = b;
+        const T a = (ra < n && ca < n) ? H[(size_t)ra * ld + ca] : T(0);
+        const T b = (rb < n && cb < n) ? H[(size_t)rb * ld + cb] : T(0);
+        bad |= !isfinite((double)a) | !isfinite((double)b);
+        sA[rr][cc] = (L)a;
+        sB[rr][cc] = (L)b;
     }
 }
 
@@ -35,15 +47,16 @@ __device__ inline void load_pair(const T* __restrict__ H, int n, int ld, int I, 
 // the 64 columns of column tile K of |Hs_ij|, j != i: rows of I from the
 // columns of J, and (I != J) rows of J from the columns of I.  Four threads
 // per row, 16 columns each, combined in a fixed pattern.
-__device__ inline void pair_row_partials(int n, int I, int J, double (*sA)[kBndTile + 1],
-                                         double (*sB)[kBndTile + 1], double* __restrict__ rowpart,
+template <typename L>
+__device__ inline void pair_row_partials(int n, int I, int J, L (*sA)[kBndTile + 1],
+                                         L (*sB)[kBndTile + 1], double* __restrict__ rowpart,
                                          int ldp) {
     const int tid = threadIdx.x, r = tid >> 2, q = tid & 3;
     double acc = 0.0;
     const int gi = I * kBndTile + r;
     for (int j = 0; j < 16; ++j) {
         const int c = q * 16 + j, gj = J * kBndTile + c;
-        const double hs = (sA[r][c] + sB[c][r]) / 2.0;
+        const double hs = ((double)sA[r][c] + (double)sB[c][r]) / 2.0;
         if (gj != gi && gj < n && gi < n) acc += fabs(hs);
     }
     acc += __shfl_xor(acc, 1, 64);
@@ -55,7 +68,7 @@ __device__ inline void pair_row_partials(int n, int I, int J, double (*sA)[kBndT
         const int gj = J * kBndTile + r;
         for (int i = 0; i < 16; ++i) {
             const int c = q * 16 + i, gi2 = I * kBndTile + c;
-            const double hs = (sA[c][r] + sB[r][c]) / 2.0;
+            const double hs = ((double)sA[c][r] + (double)sB[r][c]) / 2.0;
             if (gi2 < n && gj < n) acc2 += fabs(hs);
         }
         acc2 += __shfl_xor(acc2, 1, 64);
@@ -65,11 +78,13 @@ __device__ inline void pair_row_partials(int n, int I, int J, double (*sA)[kBndT
 }
 
 // X_0 of one tile pair of the padded ldp x ldp FP64 buffer (zero outside
-// n x n): tile (I, J) directly, tile (J, I) as its transpose through LDS, so
-// X_0 is bitwise symmetric.  The pair's trace and ||X_0||^2 (the off-diagonal
-// pair counted twice) go to pairpart[2 p], [2 p + 1].
+// n x n): tile (I, J) directly, tile (J, I) as its transpose through the FP64
+// LDS tile sT (which may alias sA and sB: it is written only after both are
+// read), so X_0 is bitwise symmetric.  The pair's trace and ||X_0||^2 (the
+// off-diagonal pair counted twice) go to pairpart[2 p], [2 p + 1].
+template <typename L>
 __device__ inline void pair_x0(int n, int ldp, int I, int J, double emax, double width,
-                               double (*sA)[kBndTile + 1], double (*sB)[kBndTile + 1],
+                               L (*sA)[kBndTile + 1], L (*sB)[kBndTile + 1], double (*sT)[kBndTile + 1],
                                double* __restrict__ X0, double* red, double* pairpart, unsigned p) {
     const int tid = threadIdx.x;
     double xv[kBndTile * kBndTile / kThreads];
@@ -81,7 +96,7 @@ __device__ inline void pair_x0(int n, int ldp, int I, int J, double emax, double
         const int gi = I * kBndTile + rr, gj = J * kBndTile + cc;
         double x = 0.0;
         if (gi < n && gj < n) {
-            const double hs = (sA[rr][cc] + sB[cc][rr]) / 2.0;
+            const double hs = ((double)sA[rr][cc] + (double)sB[cc][rr]) / 2.0;
             const double num = (gi == gj) ? (emax - hs) : (0.0 - hs);
             x = num / width;
         }
@@ -99,11 +114,11 @@ __device__ inline void pair_x0(int n, int ldp, int I, int J, double emax, double
     if (I != J) {
         __syncthreads();
         k = 0;
-        for (int e = tid; e < kBndTile * kBndTile; e += kThreads, ++k) sA[e >> 6][e & 63] = xv[k];
+        for (int e = tid; e < kBndTile * kBndTile; e += kThreads, ++k) sT[e >> 6][e & 63] = xv[k];
         __syncthreads();
         for (int e = tid; e < kBndTile * kBndTile; e += kThreads) {
             const int rr = e >> 6, cc = e & 63;
-            X0[(size_t)(J * kBndTile + rr) * ldp + I * kBndTile + cc] = sA[cc][rr];
+            X0[(size_t)(J * kBndTile + rr) * ldp + I * kBndTile + cc] = sT[cc][rr];
         }
     }
 }

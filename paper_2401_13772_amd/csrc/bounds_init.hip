@@ -32,8 +32,9 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bounds_pair(const T* __restrict__ H, int n, int ld,
                                                           double* __restrict__ rowpart, int ldp,
                                                           State* st) {
-    __shared__ double sA[kBndTile][kBndTile + 1];
-    __shared__ double sB[kBndTile][kBndTile + 1];
+    typedef typename PairLds<T>::type L;
+    __shared__ L sA[kBndTile][kBndTile + 1];
+    __shared__ L sB[kBndTile][kBndTile + 1];
     int I, J;
     tri_tile(blockIdx.x, I, J);
     int bad = 0;
@@ -99,8 +100,15 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_init_pair(const T* __restrict__ H, int n, int ld, int ldp,
                                                         double* __restrict__ X0, double* __restrict__ part,
                                                         const State* st) {
-    __shared__ double sA[kBndTile][kBndTile + 1];
-    __shared__ double sB[kBndTile][kBndTile + 1];
+    typedef typename PairLds<T>::type L;
+    // two L tiles, later one FP64 tile for the transposed write (FP32 storage:
+    // the two FP32 tiles and the FP64 tile share the same 33 KB)
+    constexpr int kTileElems = kBndTile * (kBndTile + 1);
+    constexpr int kRaw = sizeof(L) == sizeof(double) ? 2 * kTileElems : kTileElems;
+    __shared__ double raw[kRaw];
+    L (*sA)[kBndTile + 1] = (L (*)[kBndTile + 1])raw;
+    L (*sB)[kBndTile + 1] = (L (*)[kBndTile + 1])((L*)raw + kTileElems);
+    double (*sT)[kBndTile + 1] = (double (*)[kBndTile + 1])raw;
     __shared__ double red[4];
     int I, J;
     tri_tile(blockIdx.x, I, J);
@@ -108,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_init_pair(const T* __restrict__ H,
     int bad = 0;
     load_pair(H, n, ld, I, J, sA, sB, bad);
     __syncthreads();
-    pair_x0(n, ldp, I, J, emax, width, sA, sB, X0, red, part, blockIdx.x);
+    pair_x0(n, ldp, I, J, emax, width, sA, sB, sT, X0, red, part, blockIdx.x);
 }
 
 // tr X_0 and ||X_0||^2 from the pair partials in pair order (one block), and

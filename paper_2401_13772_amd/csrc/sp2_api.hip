@@ -12,25 +12,73 @@
 // instruction.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "sp2_internal.h"
 
 using namespace sp2;
 
+namespace sp2 {
+
+constexpr int kSlotDevices = 16;
+
+struct SlotPool {
+    std::mutex m;
+    std::vector<HostSlots*> free_sets[kSlotDevices];
+};
+
+static SlotPool& slot_pool() {
+    static SlotPool* p = new SlotPool;
+    return *p;
+}
+
+SlotLease::~SlotLease() {
+    if (s) {
+        if (has_pending) (void)hipStreamSynchronize(pending);   // error paths only
+        SlotPool& p = slot_pool();
+        std::lock_guard<std::mutex> g(p.m);
+        p.free_sets[dev].push_back(s);
+    }
+}
+
+hipError_t slots_for_current(SlotLease& lease) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kSlotDevices) return hipErrorInvalidDevice;
+    SlotPool& p = slot_pool();
+    {
+        std::lock_guard<std::mutex> g(p.m);
+        if (!p.free_sets[dev].empty()) {
+            lease.s = p.free_sets[dev].back();
+            lease.dev = dev;
+            p.free_sets[dev].pop_back();
+            return hipSuccess;
+        }
+    }
+    HostSlots* s = new HostSlots;
+    e = hipHostMalloc((void**)&s->flags, 2 * sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->state, sizeof(State), hipHostMallocDefault);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        for (int i = 0; i < 2; ++i)
+            if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
+        if (s->state) (void)hipHostFree(s->state);
+        if (s->flags) (void)hipHostFree(s->flags);
+        delete s;
+        return e;
+    }
+    lease.s = s;
+    lease.dev = dev;
+    return hipSuccess;
+}
+
+}  // namespace sp2
+
 namespace {
 
 constexpr int kMaxDevices = 16;
-
-// Per-thread, per-device pinned status buffer and events, made on first use
-// and kept until the thread ends.
-struct HostSlots {
-    int* flags = nullptr;     // 2 pinned ints
-    State* state = nullptr;   // pinned copy of the device state
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    bool ready = false;
-};
-
-thread_local HostSlots t_slots[kMaxDevices];
 
 // Optional per-step kernel timing (sp2_profile_enable): an event pair around
 // every SYRK launch on the caller's stream.
@@ -62,26 +110,6 @@ hipError_t profile_for_current(Profile** out) {
     return hipSuccess;
 }
 
-hipError_t slots_for_current(HostSlots** out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    HostSlots& s = t_slots[dev];
-    if (!s.ready) {
-        e = hipHostMalloc((void**)&s.flags, 2 * sizeof(int), hipHostMallocDefault);
-        if (e != hipSuccess) return e;
-        e = hipHostMalloc((void**)&s.state, sizeof(State), hipHostMallocDefault);
-        if (e != hipSuccess) return e;
-        for (int i = 0; i < 2; ++i) {
-            e = hipEventCreateWithFlags(&s.ev[i], hipEventDisableTiming);
-            if (e != hipSuccess) return e;
-        }
-        s.ready = true;
-    }
-    *out = &s;
-    return hipSuccess;
-}
 
 bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
     const char* pa = (const char*)a;
@@ -130,12 +158,23 @@ static bool compute_built(sp2_compute c) {
     return c == SP2_C_F64 || c == SP2_C_F16X2 || c == SP2_C_BF16X3 || c == SP2_C_BF16X2 || c == SP2_C_FP8;
 }
 
-// FP64 steps before the split phase when the caller passes -1: enough for the
-// spectral gap, mapped into [0, 1], to have opened to O(1) so that later
-// rounding errors are no longer amplified by the remaining steps.
-static int auto_prefix(int n) {
-    (void)n;
-    return 12;
+// FP64 steps before the split phase when the caller passes -1.  An error made
+// at step m reaches D multiplied by about 1 / (the HOMO-LUMO gap mapped into
+// [0, 1] by the first m steps), so the split phase starts once that gap has
+// opened.  Calibrated on MI355X against FP64 SP2 and LAPACK on tight-binding
+// Hamiltonians (n = 1024..4096, gaps 0.3 and 0.5 eV on a ~140 eV Gershgorin
+// interval), keeping rms |D - D_ref| at least 1.4x below 1e-6:
+//   F16X2  m0 = 8  -> 5.8e-7 (0.5 eV), 7.0e-7 (0.3 eV) at n = 4096;
+//   BF16X3 m0 = 6  -> 4.3e-7, 5.3e-7.
+// The error grows slowly with n, so larger n take two more steps.  BF16X2 and
+// FP8 cannot reach 1e-6 whatever m0 (their planes hold ~8-16 bits).
+static int auto_prefix(int n, sp2_compute compute) {
+    const int extra = n > 4096 ? 2 : 0;
+    switch (compute) {
+        case SP2_C_F16X2: return 8 + extra;
+        case SP2_C_BF16X3: return 6 + extra;
+        default: return 8 + extra;
+    }
 }
 
 size_t sp2_workspace_size(int n, sp2_dtype dtype, sp2_compute compute) {
@@ -173,7 +212,9 @@ int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, i
     if (fp64_prefix_iters < -1 || fp64_prefix_iters > SP2_MAX_ITER) return fail(info, SP2_E_INVALID);
     const Layout L = make_layout(n, compute);
     const bool mixed = L.np > 0;
-    const int m0 = mixed ? (fp64_prefix_iters < 0 ? auto_prefix(n) : (fp64_prefix_iters < 1 ? 1 : fp64_prefix_iters)) : 0;
+    const int m0 = mixed ? (fp64_prefix_iters < 0 ? auto_prefix(n, compute)
+                                                  : (fp64_prefix_iters < 1 ? 1 : fp64_prefix_iters))
+                         : 0;
     if (!workspace || workspace_bytes < L.total ||
         (reinterpret_cast<uintptr_t>(workspace) % SP2_WORKSPACE_ALIGN) != 0)
         return fail(info, SP2_E_WORKSPACE);
@@ -193,12 +234,13 @@ int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, i
     void* p0 = ws + L.off_p0;
     void* p1 = ws + L.off_p1;
 
-    HostSlots* hs = nullptr;
+    SlotLease lease;
     Profile* prof = nullptr;
     if (!no_alloc) {
-        SP2_HIP(slots_for_current(&hs));
+        SP2_HIP(slots_for_current(lease));
         SP2_HIP(profile_for_current(&prof));
     }
+    HostSlots* hs = lease.s;
     const bool timed = prof && prof->on;
 
     SP2_HIP(launch_reset(st, n, n_occ, tol, max_iter, m0, cnt, L.max_groups + 2, s));
@@ -232,6 +274,8 @@ int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, i
             if (timed) SP2_HIP(hipEventRecord(ev[1], s));
         }
         if (no_alloc) continue;
+        lease.pending = s;
+        lease.has_pending = true;
         SP2_HIP(hipMemcpyAsync(&hs->flags[slot], &st->done, sizeof(int), hipMemcpyDeviceToHost, s));
         SP2_HIP(hipEventRecord(hs->ev[slot], s));
         if (pending >= 0) {
@@ -244,8 +288,13 @@ int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, i
     SP2_HIP(launch_finalize(D, dtype, n, ld, L, compute, st, x0, x1, p0, p1, s));
     static thread_local State t_state;   // pageable: the no-allocation path
     State* hstate = no_alloc ? &t_state : hs->state;
+    if (!no_alloc) {
+        lease.pending = s;
+        lease.has_pending = true;
+    }
     SP2_HIP(hipMemcpyAsync(hstate, st, sizeof(State), hipMemcpyDeviceToHost, s));
     SP2_HIP(hipStreamSynchronize(s));
+    lease.has_pending = false;
 
     const State& h = *hstate;
     if (timed) {
@@ -311,11 +360,15 @@ int sp2_history(const void* workspace, int count, double* tr_hist, double* e_his
     sp2_info* info = nullptr;
     if (!workspace || count < 0) return SP2_E_INVALID;
     if ((reinterpret_cast<uintptr_t>(workspace) % SP2_WORKSPACE_ALIGN) != 0) return SP2_E_WORKSPACE;
-    HostSlots* hs = nullptr;
-    SP2_HIP(slots_for_current(&hs));
+    SlotLease lease;
+    SP2_HIP(slots_for_current(lease));
+    HostSlots* hs = lease.s;
     hipStream_t s = (hipStream_t)hip_stream;
+    lease.pending = s;
+    lease.has_pending = true;
     SP2_HIP(hipMemcpyAsync(hs->state, workspace, sizeof(State), hipMemcpyDeviceToHost, s));
     SP2_HIP(hipStreamSynchronize(s));
+    lease.has_pending = false;
     const State& h = *hs->state;
     int m = h.iterations < count ? h.iterations : count;
     if (m > SP2_MAX_ITER) m = SP2_MAX_ITER;

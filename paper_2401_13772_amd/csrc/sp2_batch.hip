@@ -34,6 +34,7 @@
 // single-matrix path's shape (64 x 64 tiles, 4 waves), so every matrix's D is
 // bitwise equal to its sp2_density solve.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -52,7 +53,8 @@ struct BatchMat {
     double* part;
     double* rowpart;   // Gershgorin row partials, (ldp / 64) x ldp
     State* st;
-    int n, ldp, n_occ, pad;
+    int n, ldp, n_occ, mu_mode;
+    double mu;         // mu_mode: the chemical potential, written by every run
 };
 
 // ---------------------------------------------------------------- kernels
@@ -63,7 +65,8 @@ __global__ void k_batch_reset(BatchMat* mats, int batch, double tol, int max_ite
                               double idem_fallback) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
-    if (n_layers < 0) state_reset(mats[b].st, mats[b].n, mats[b].n_occ, tol, max_iter, 0);
+    if (mats[b].mu_mode) state_reset_mu(mats[b].st, mats[b].n, mats[b].mu, tol, max_iter);
+    else if (n_layers < 0) state_reset(mats[b].st, mats[b].n, mats[b].n_occ, tol, max_iter, 0);
     else state_reset_learned(mats[b].st, mats[b].n, mats[b].n_occ, tol, max_iter, n_layers, idem_fallback);
 }
 
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_bounds_init(const BatchMat* 
         __syncthreads();
         load_pair(H, n, ld, I, J, sA, sB, bad);
         __syncthreads();
-        pair_x0(n, ldp, I, J, emax, width, sA, sB, M.x0, bred, M.part, p);
+        pair_x0(n, ldp, I, J, emax, width, sA, sB, sA, M.x0, bred, M.part, p);
     }
     __threadfence();
     __syncthreads();
@@ -240,7 +243,7 @@ __global__ void k_batch_info(const BatchMat* __restrict__ mats, int batch, sp2_i
     r.fp64_prefix_iters = st->fp64_steps;
     r.refine_steps = st->refine_steps;
     r.trace = st->tr;
-    r.trace_error = fabs(st->tr - st->nocc);
+    r.trace_error = st->mu_mode ? 0.0 : fabs(st->tr - st->nocc);
     r.idempotency = st->idem;
     r.emin = st->emin;
     r.emax = st->emax;
@@ -297,6 +300,7 @@ struct sp2_plan {
     double* d_coef = nullptr;         // learned expansion: 3 per layer
     int n_layers = -1;                // -1: plain SP2
     double idem_fallback = 0.0;
+    int mu_mode = 0;                  // 1: steered by a chemical potential per run
     sp2::BatchMat* h_mats = nullptr;  // pinned
     sp2_info* h_infos = nullptr;      // pinned
     hipGraph_t graph = nullptr;
@@ -452,10 +456,11 @@ namespace sp2 {
 // up to max_iter steps in all.
 int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ, sp2_dtype dtype,
                      sp2_compute compute, double tol, int max_iter, const char* autotune_cache,
-                     const double* coef, int n_layers, double idem_fallback) {
+                     const double* coef, int n_layers, double idem_fallback, int mu_mode) {
     if (!plan) return SP2_E_INVALID;
     *plan = nullptr;
-    if (batch <= 0 || batch > SP2_PLAN_MAX_BATCH || !n || !n_occ) return SP2_E_INVALID;
+    if (batch <= 0 || batch > SP2_PLAN_MAX_BATCH || !n || (!n_occ && !mu_mode)) return SP2_E_INVALID;
+    if (mu_mode && n_layers >= 0) return SP2_E_INVALID;
     if (dtype != SP2_F64 && dtype != SP2_F32) return SP2_E_INVALID;
     if (!(tol > 0.0) || !(tol < 1e300) || max_iter < 0 || max_iter > SP2_MAX_ITER) return SP2_E_INVALID;
     if (n_layers >= 0 && (n_layers + 1 > max_iter || (n_layers > 0 && !coef) || !(idem_fallback > 0.0)))
@@ -463,7 +468,8 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
     if (compute < SP2_C_F64 || compute > SP2_C_FP8) return SP2_E_INVALID;
     if (compute != SP2_C_F64) return SP2_E_UNSUPPORTED;
     for (int b = 0; b < batch; ++b)
-        if (n[b] <= 0 || n[b] > SP2_PLAN_MAX_N || n_occ[b] < 0 || n_occ[b] > n[b]) return SP2_E_INVALID;
+        if (n[b] <= 0 || n[b] > SP2_PLAN_MAX_N || (!mu_mode && (n_occ[b] < 0 || n_occ[b] > n[b])))
+            return SP2_E_INVALID;
 
     sp2_plan* p = new (std::nothrow) sp2_plan;
     if (!p) return SP2_E_HIP;
@@ -474,6 +480,7 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
     p->max_iter = max_iter;
     p->n_layers = n_layers;
     p->idem_fallback = idem_fallback;
+    p->mu_mode = mu_mode;
     p->n.assign(n, n + batch);
     if (hipGetDevice(&p->device) != hipSuccess) {
         plan_free(p);
@@ -535,8 +542,9 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
         m.x1 = m.x0 + (size_t)ldp[k] * ldp[k];
         m.n = n[p->order[k]];
         m.ldp = ldp[k];
-        m.n_occ = n_occ[p->order[k]];
-        m.pad = 0;
+        m.n_occ = mu_mode ? 0 : n_occ[p->order[k]];
+        m.mu_mode = mu_mode;
+        m.mu = 0.0;
     }
     hipStream_t s = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
@@ -600,11 +608,32 @@ extern "C" {
 int sp2_plan_create(sp2_plan** plan, int batch, const int* n, const int* n_occ, sp2_dtype dtype,
                     sp2_compute compute, double tol, int max_iter, const char* autotune_cache) {
     return sp2::plan_create_impl(plan, batch, n, n_occ, dtype, compute, tol, max_iter, autotune_cache,
-                                 nullptr, -1, 0.0);
+                                 nullptr, -1, 0.0, 0);
 }
 
 int sp2_plan_run(sp2_plan* p, const void* const* H, void* const* D, void* hip_stream, sp2_info* infos) {
+    return sp2::plan_run_impl(p, H, D, nullptr, hip_stream, infos);
+}
+
+const char* sp2_plan_config(const sp2_plan* p) { return p ? p->cfg_name : ""; }
+
+int sp2_plan_destroy(sp2_plan* p) {
+    if (!p) return SP2_E_INVALID;
+    plan_free(p);
+    return SP2_OK;
+}
+
+}  // extern "C"
+
+namespace sp2 {
+
+// One solve of every matrix of the plan.  mu (caller order) sets the chemical
+// potential of each matrix of a plan made with mu_mode; it must be null
+// otherwise.
+int plan_run_impl(sp2_plan* p, const void* const* H, void* const* D, const double* mu, void* hip_stream,
+                  sp2_info* infos) {
     if (!p || !H || !D) return SP2_E_INVALID;
+    if ((mu != nullptr) != (p->mu_mode != 0)) return SP2_E_INVALID;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SP2_E_HIP;
     if (dev != p->device) return SP2_E_INVALID;
@@ -616,8 +645,10 @@ int sp2_plan_run(sp2_plan* p, const void* const* H, void* const* D, void* hip_st
         const char* h = (const char*)H[b];
         const char* d = (const char*)D[b];
         if (h < d + bytes && d < h + bytes) return SP2_E_INVALID;
+        if (mu && !std::isfinite(mu[b])) return SP2_E_INVALID;
         p->h_mats[k].H = H[b];
         p->h_mats[k].D = D[b];
+        p->h_mats[k].mu = mu ? mu[b] : 0.0;
     }
     hipStream_t s = (hipStream_t)hip_stream;
     if (hipMemcpyAsync(p->d_mats, p->h_mats, p->batch * sizeof(BatchMat), hipMemcpyHostToDevice, s) !=
@@ -639,12 +670,4 @@ int sp2_plan_run(sp2_plan* p, const void* const* H, void* const* D, void* hip_st
     return neg < 0 ? neg : pos;
 }
 
-const char* sp2_plan_config(const sp2_plan* p) { return p ? p->cfg_name : ""; }
-
-int sp2_plan_destroy(sp2_plan* p) {
-    if (!p) return SP2_E_INVALID;
-    plan_free(p);
-    return SP2_OK;
-}
-
-}  // extern "C"
+}  // namespace sp2

@@ -217,6 +217,20 @@ __device__ inline void state_reset(State* st, int n, int n_occ, double tol, int 
     st->n_layers = 0;
     st->pad1 = 0;
     st->idem_fallback = 0.0;
+    st->mu_mode = 0;
+    st->pad2 = 0;
+    st->mu = 0.0;
+    st->xmu = 0.0;
+    st->sp_slices = 0ull;
+    st->sp_tiles = 0ull;
+}
+
+// Start of a solve steered by a chemical potential mu (one thread): the
+// density matrix is the projector on the eigenvalues below mu.
+__device__ inline void state_reset_mu(State* st, int n, double mu, double tol, int max_iter) {
+    state_reset(st, n, 0, tol, max_iter, 0);
+    st->mu_mode = 1;
+    st->mu = mu;
 }
 
 // Start of a learned-expansion solve: n_layers trained layers, then an SP2
@@ -256,6 +270,33 @@ __device__ inline void state_after_init(State* st, double t, double f) {
     st->fro2 = f;
     st->grow = (t - st->nocc <= 0.0) ? 1 : 0;
     const int nn = st->n;
+    if (st->mu_mode) {
+        // mu's image under X_0 = (emax I - H)/(emax - emin); eigenvalues above
+        // x_mu (energies below mu) go to 1.  mu outside the Gershgorin
+        // interval: every level lies on one side of it, D = 0 or I exactly.
+        const double w = st->emax - st->emin;
+        st->xmu = w > 0.0 ? (st->emax - st->mu) / w : 0.5;
+        st->grow = st->xmu <= 0.5 ? 1 : 0;
+        if (st->bad) {
+            st->status = SP2_E_INVALID;
+            st->done = 1;
+        } else if (st->mu <= st->emin) {
+            st->special = 1;
+            st->status = SP2_OK;
+            st->done = 1;
+            st->tr = 0.0;
+        } else if (st->mu >= st->emax) {
+            st->special = 2;
+            st->status = SP2_OK;
+            st->done = 1;
+            st->tr = (double)nn;
+        } else if (st->max_iter == 0) {
+            st->status = SP2_E_NOT_CONVERGED;
+            st->done = 1;
+        }
+        st->ticket = 0;
+        return;
+    }
     if (st->bad) {
         st->status = SP2_E_INVALID;
         st->done = 1;
@@ -300,15 +341,31 @@ __device__ __forceinline__ void sp2_steer_thread0(State* st, double E, double TR
     st->tr = TR;
     st->fro2 = F;
     st->idem = e;
-    const int trace_grow = (TR - st->nocc <= 0.0) ? 1 : 0;
+    int trace_grow = (TR - st->nocc <= 0.0) ? 1 : 0;
+    if (st->mu_mode) {
+        // follow mu's image through the map just applied; the next branch
+        // pulls it back towards 1/2 (x_mu above 1/2: x^2, else 2x - x^2)
+        const double x = st->xmu;
+        const double xn = grow ? x * (2.0 - x) : x * x;
+        st->xmu = xn;
+        trace_grow = xn <= 0.5 ? 1 : 0;
+    }
     const int phase = st->phase;
     if (phase == 0) {
         st->fp64_steps = st->fp64_steps + 1;
         st->grow = trace_grow;
+        // stagnation: no progress over two steps once every eigenvalue is
+        // near 0 or 1.  Steered by mu, the branch follows mu's image, which
+        // takes at most two equal branches in a row: levels on the side the
+        // branch pushes away from 0 or 1 can grow for two steps before the
+        // other branch squares their distance, so there the test spans three
+        // steps and waits for e < 1e-3.
+        const int stag_span = st->mu_mode ? 3 : 2;
+        const double stag_below = st->mu_mode ? 1e-3 : 0.1;
         if (e <= st->tol) {
             st->done = 1;
             st->status = SP2_OK;
-        } else if (m >= 2 && e >= st->e_hist[m - 2] && e < 0.1) {
+        } else if (m >= stag_span && e >= st->e_hist[m - stag_span] && e < stag_below) {
             st->done = 1;
             st->status = SP2_E_STAGNATED;
         } else if (m + 1 >= st->max_iter) {

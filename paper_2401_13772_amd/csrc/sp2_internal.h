@@ -47,6 +47,16 @@ struct State {
     int32_t n_layers;
     int32_t pad1;
     double idem_fallback;  // the check step's idempotency bar
+    // steering by a chemical potential instead of the occupation: the branch
+    // follows mu's image x_mu under the maps applied so far (graph parts)
+    int32_t mu_mode;
+    int32_t pad2;
+    double mu;
+    double xmu;
+    // thresholded SP2: K slices multiplied and output tiles computed, summed
+    // over the steps of the solve
+    unsigned long long sp_slices;
+    unsigned long long sp_tiles;
     uint64_t branch_mask[2];
     uint64_t lp_mask[2];  // bit m set when step m was a split-operand step
     double tr_hist[SP2_MAX_ITER];
@@ -58,6 +68,7 @@ struct Layout {
     int n, ldp, bt;          // padded edge, FP64 SYRK tile edge
     int tiles;               // lower tiles of the FP64 SYRK grid
     int max_groups;          // stream-K grid bound: min(tiles, kMaxPersistent)
+    int lp_groups;           // grid bound of the split-operand kernel (0: FP64 only)
     int np;                  // split-operand planes per iterate (0: FP64 only)
     int pb;                  // bytes per plane element
     size_t plane_stride;     // elements between planes of one iterate (ldp^2)
@@ -103,7 +114,11 @@ inline Layout make_layout(int n, sp2_compute compute) {
     L.off_rowpart = off; off = align_up(off + ((size_t)nbt * L.ldp + 2 * (size_t)L.ldp) * sizeof(double), 256);
     size_t scratch_f64 = 2 * (size_t)(L.max_groups + 1) * L.bt * L.bt * sizeof(double);
     int Tl = L.ldp / kLpTile;
+    // split-operand grid: one workgroup per 128-tile for n <= 2048, the full
+    // persistent grid above (the FP64 scratch is already that large there)
     int lp_groups = Tl * (Tl + 1) / 2 < kMaxPersistent ? Tl * (Tl + 1) / 2 : kMaxPersistent;
+    if (L.bt == 128) lp_groups = kMaxPersistent;
+    L.lp_groups = L.np ? lp_groups : 0;
     size_t scratch_lp = L.np ? 2 * (size_t)(lp_groups + 1) * kLpTile * kLpTile * sizeof(double) : 0;
     if (L.np && lp_groups > L.max_groups) L.max_groups = lp_groups;
     L.off_cnt = off;     off = align_up(off + (size_t)(L.max_groups + 2) * sizeof(unsigned), 256);
@@ -172,10 +187,36 @@ int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, i
                  sp2_dtype dtype, sp2_compute compute, int fp64_prefix_iters, void* workspace,
                  size_t workspace_bytes, void* hip_stream, sp2_info* info, bool no_alloc);
 
+// Pinned status buffers and events of one in-flight call.  Calls take a set
+// from a per-device free list and give it back when they return, so the sets
+// made equal the largest number of concurrent calls on a device, whatever
+// the number of threads that ever called; they are reused for the life of
+// the process (the pool is never destroyed, so no HIP call runs during
+// static destruction).
+struct HostSlots {
+    int* flags = nullptr;     // 2 pinned ints
+    State* state = nullptr;   // pinned copy of the device state
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+// Holds one set for the duration of a call.
+struct SlotLease {
+    HostSlots* s = nullptr;
+    int dev = -1;
+    hipStream_t pending = nullptr;   // a copy into the set may still be queued here
+    bool has_pending = false;
+    ~SlotLease();
+};
+
+// Takes a set of the current device's pool (made on first use).
+hipError_t slots_for_current(SlotLease& lease);
+
 // The batched plan behind sp2_plan_create and the learned expansion (sp2_batch.hip).
 int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ, sp2_dtype dtype,
                      sp2_compute compute, double tol, int max_iter, const char* autotune_cache,
-                     const double* coef, int n_layers, double idem_fallback);
+                     const double* coef, int n_layers, double idem_fallback, int mu_mode);
+int plan_run_impl(sp2_plan* p, const void* const* H, void* const* D, const double* mu, void* hip_stream,
+                  sp2_info* infos);
 
 // ---------------------------------------------------------------- host launchers
 

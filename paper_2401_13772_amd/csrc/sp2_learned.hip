@@ -363,7 +363,7 @@ int sp2_learned_density(sp2_learned* model, int batch, int n, const void* const*
         if (max_iter > SP2_MAX_ITER) max_iter = SP2_MAX_ITER;
         const int st = sp2::plan_create_impl(&model->plan, batch, ns.data(), n_occ, dtype, SP2_C_F64, 1e-10,
                                              max_iter, nullptr, model->coef.data(), model->n_layers,
-                                             idem_fallback);
+                                             idem_fallback, 0);
         if (st != SP2_OK) return st;
         model->key_batch = batch;
         model->key_n = n;

@@ -203,8 +203,11 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64_hyb(const double* __restrict
         const unsigned U = R * (unsigned)KT;
         const unsigned minr = KT >= 16 ? (unsigned)KT / 16u : 1u;
         const unsigned Gs = (U / minr < G) ? (U / minr > 0 ? U / minr : 1u) : G;
-        const unsigned u0 = g < Gs ? (U * g) / Gs : U;
-        const unsigned u1 = g < Gs ? (U * (g + 1)) / Gs : U;
+        // remainder owners by hardware block index: blocks are dealt round-robin
+        // to the XCDs, so the Gs owners spread over all of them
+        const unsigned gr = blockIdx.x;
+        const unsigned u0 = gr < Gs ? (U * gr) / Gs : U;
+        const unsigned u1 = gr < Gs ? (U * (gr + 1)) / Gs : U;
         unsigned u = u0;
         int seg_no = 0;
         while (u < u1) {
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64_hyb(const double* __restrict
             const unsigned ga = ((ts + 1) * Gs - 1) / U;
             const unsigned gb = (te * Gs - 1) / U;
             const size_t tile_elems = (size_t)C::BT * C::BT;
-            d4* mine = (d4*)(scratch + (2 * (size_t)g + slot) * tile_elems);
+            d4* mine = (d4*)(scratch + (2 * (size_t)gr + slot) * tile_elems);
 #pragma unroll
             for (int mi = 0; mi < C::MI; ++mi)
 #pragma unroll

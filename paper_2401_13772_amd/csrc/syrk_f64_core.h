@@ -269,10 +269,16 @@ struct LdsEpi {
     static_assert(C::WTM == HR && C::WM * HR == C::BT, "one pass per row of waves");
 };
 
-template <class C>
+// Entry kept by the drop threshold (|v| >= tau).
+__device__ __forceinline__ double keep_large(double v, double tau) { return fabs(v) < tau ? 0.0 : v; }
+
+// PRUNE: the thresholded update of the SP2 listing's cutoff: S' = drop(S),
+// X' = drop(2X - S') or S', e^2 from S' - X; nz is set when X' has a nonzero.
+template <class C, bool PRUNE = false>
 __device__ __forceinline__ void sp2_epilogue_lds(const double* __restrict__ X, double* __restrict__ Y, int ldp,
                                                  int ti, int tj, int grow, const d4 (&acc)[C::MI][C::NI],
-                                                 double* Cs, double& e2, double& trp, double& fro) {
+                                                 double* Cs, double& e2, double& trp, double& fro,
+                                                 double tau = 0.0, int* nz = nullptr) {
     using E = LdsEpi<C>;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w / C::WN, wn = w % C::WN;
@@ -305,10 +311,15 @@ __device__ __forceinline__ void sp2_epilogue_lds(const double* __restrict__ X, d
 #pragma unroll
             for (int k = 0; k < RUN; ++k) {
                 const int c = c0 + k;
-                const double sv = Cs[r * E::CLD + c];
+                double sv = Cs[r * E::CLD + c];
+                if constexpr (PRUNE) sv = keep_large(sv, tau);
                 const double x = xv[k];
                 const double d = sv - x;
-                const double xn = grow ? (2.0 * x - sv) : sv;
+                double xn = grow ? (2.0 * x - sv) : sv;
+                if constexpr (PRUNE) {
+                    if (grow) xn = keep_large(xn, tau);
+                    if (xn != 0.0 && (!diag || c <= lr)) *nz = 1;
+                }
                 const double wgt = diag ? (c < lr ? 2.0 : (c == lr ? 1.0 : 0.0)) : 2.0;
                 e2 += wgt * (d * d);
                 fro += wgt * (xn * xn);
@@ -333,9 +344,14 @@ __device__ __forceinline__ void sp2_epilogue_lds(const double* __restrict__ X, d
             bool any = false;
 #pragma unroll
             for (int k = 0; k < RUN; ++k) {
-                const double sv = Cs[(r0 + k) * E::CLD + c];
+                double sv = Cs[(r0 + k) * E::CLD + c];
+                if constexpr (PRUNE) sv = keep_large(sv, tau);
                 const double x = xv[k];
-                out[k] = grow ? (2.0 * x - sv) : sv;
+                double xn = grow ? (2.0 * x - sv) : sv;
+                if constexpr (PRUNE) {
+                    if (grow) xn = keep_large(xn, tau);
+                }
+                out[k] = xn;
                 any |= !diag || (c < h * E::HR + r0 + k);
             }
             if (!diag) {

@@ -30,9 +30,11 @@
 //     chunks are stored XOR-swizzled by (row >> 1) & 3 so that the eight lanes
 //     a ds_read_b128 serves per cycle hit distinct banks;
 //   * double-buffered K slices of 32 elements, one barrier per slice;
-//   * the same stream-K schedule, XCD renumbering and order-independent
-//     split-tile fix-up as the FP64 step, with FP64 partial tiles.
-#include "sp2_device.h"
+//   * the schedule of the 128-tile FP64 step: grouped raster, K-synchronous
+//     data-parallel waves (the workgroups of one XCD share panels in L2) and
+//     a stream-K remainder with an order-independent fix-up of FP64 partial
+//     tiles.
+#include "syrk_f64_core.h"
 
 namespace sp2 {
 
@@ -292,18 +294,13 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __res
     const unsigned g = xcd_remap(blockIdx.x, G);
     const int KT = ldp / C::KE;
     const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
-    const uint64_t U = (uint64_t)ntiles * KT;
-    const uint64_t u0 = U * g / G, u1 = U * (g + 1) / G;
+    const unsigned waves = ntiles / G;
+    const unsigned Dt = waves * G;
+    const unsigned R = ntiles - Dt;
     const int tid = threadIdx.x;
+    double* Cs = (double*)lsmem;       // the stage buffers are free after a main loop
 
-    uint64_t u = u0;
-    while (u < u1) {
-        const unsigned t = (unsigned)(u / KT);
-        const int k0 = (int)(u % KT);
-        const uint64_t kend = (uint64_t)k0 + (u1 - u);
-        const int k1 = kend < (uint64_t)KT ? (int)kend : KT;
-        int ti, tj;
-        tri_tile(t, ti, tj);
+    auto run = [&](unsigned t, int ti, int tj, int k0, int k1) {
         d4 acc[C::MI][C::NI];
         f4 accx[C::MI][C::NI];
 #pragma unroll
@@ -315,36 +312,10 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __res
             }
         if (ti == tj) lp_mainloop<C, true>(Pin, pstride, ldp, ti, tj, k0, k1, lsmem, acc, accx);
         else lp_mainloop<C, false>(Pin, pstride, ldp, ti, tj, k0, k1, lsmem, acc, accx);
-        u += (uint64_t)(k1 - k0);
-
-        double* Cs = (double*)lsmem;     // the stage buffers are free after the main loop
         lp_acc_to_lds<C>(acc, accx, Cs);
         __syncthreads();
-        if (!(k0 == 0 && k1 == KT)) {
-            // split tile: seg 0 = [0, kb) ends at this group's range end
-            // (boundary g + 1); seg 1 = [kb, KT) starts at its range start.
-            const int seg = (k0 == 0) ? 0 : 1;
-            const unsigned bidx = (seg == 0) ? g + 1 : g;
-            const size_t tile_elems = (size_t)C::BT * C::BT;
-            double* mine = scratch + (2 * (size_t)bidx + seg) * tile_elems;
-            const double* other = scratch + (2 * (size_t)bidx + (1 - seg)) * tile_elems;
-            for (int i = tid; i < C::BT * C::BT; i += C::NT)
-                mine[i] = Cs[(i / C::BT) * C::CLD + (i % C::BT)];
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) flag = (int)atomicAdd(&cnt[bidx], 1u);
-            __syncthreads();
-            if (flag == 0) continue;             // the other segment will finish the tile
-            __threadfence();
-            for (int i = tid; i < C::BT * C::BT; i += C::NT) {
-                double* c = &Cs[(i / C::BT) * C::CLD + (i % C::BT)];
-                const double o = other[i];
-                *c = (seg == 0) ? (*c + o) : (o + *c);
-            }
-            if (tid == 0) cnt[bidx] = 0u;
-            __syncthreads();
-        }
-
+    };
+    auto finish = [&](unsigned t, int ti, int tj) {
         double e2 = 0.0, trp = 0.0, fro = 0.0;
         lp_epilogue<C>(Pin, Pout, pstride, ldp, ti, tj, grow, Cs, e2, trp, fro);
         e2 = group_sum<C::NW>(e2, red);
@@ -354,6 +325,72 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __res
             part[4 * t + 0] = e2;
             part[4 * t + 1] = trp;
             part[4 * t + 2] = fro;
+        }
+    };
+
+    // data-parallel waves over the grouped raster: the workgroups of one XCD
+    // start their tiles at K = 0 together and share row and column panels in L2
+    for (unsigned w = 0; w < waves; ++w) {
+        const unsigned t = w * G + g;
+        int ti, tj;
+        grouped_tile(t, T, 8, ti, tj);
+        run(t, ti, tj, 0, KT);
+        finish(t, ti, tj);
+    }
+
+    // stream-K remainder (the scheme of k_syrk_f64_hyb): R * KT slices over the
+    // first Gs workgroups, ranges at least KT/16 long; each segment of a split
+    // tile is an FP64 partial tile in slot 2g (first tile of the range) or
+    // 2g + 1; the tile's last segment to arrive adds them in workgroup order
+    if (R > 0) {
+        const unsigned U = R * (unsigned)KT;
+        const unsigned minr = KT >= 16 ? (unsigned)KT / 16u : 1u;
+        const unsigned Gs = (U / minr < G) ? (U / minr > 0 ? U / minr : 1u) : G;
+        // remainder owners by hardware block index: blocks are dealt round-robin
+        // to the XCDs, so the Gs owners spread over all of them
+        const unsigned gr = blockIdx.x;
+        const unsigned u0 = gr < Gs ? (U * gr) / Gs : U;
+        const unsigned u1 = gr < Gs ? (U * (gr + 1)) / Gs : U;
+        unsigned u = u0;
+        int seg_no = 0;
+        while (u < u1) {
+            const unsigned r = u / (unsigned)KT;
+            const int k0 = (int)(u - r * (unsigned)KT);
+            const unsigned kend = (unsigned)k0 + (u1 - u);
+            const int k1 = kend < (unsigned)KT ? (int)kend : KT;
+            const unsigned t = Dt + r;
+            int ti, tj;
+            grouped_tile(t, T, 8, ti, tj);
+            run(t, ti, tj, k0, k1);
+            u += (unsigned)(k1 - k0);
+            const int slot = seg_no++;
+            if (k0 == 0 && k1 == KT) {
+                finish(t, ti, tj);
+                continue;
+            }
+            const unsigned ts = r * (unsigned)KT, te = ts + (unsigned)KT;
+            const unsigned ga = ((ts + 1) * Gs - 1) / U;
+            const unsigned gb = (te * Gs - 1) / U;
+            const size_t tile_elems = (size_t)C::BT * C::BT;
+            double* mine = scratch + (2 * (size_t)gr + slot) * tile_elems;
+            for (int i = tid; i < C::BT * C::BT; i += C::NT) mine[i] = Cs[(i / C::BT) * C::CLD + (i % C::BT)];
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) flag = (int)atomicAdd(&cnt[r], 1u);
+            __syncthreads();
+            if (flag != (int)(gb - ga)) continue;    // not the last segment to arrive
+            __threadfence();
+            for (int i = tid; i < C::BT * C::BT; i += C::NT) {
+                double v = 0.0;
+                for (unsigned q = ga; q <= gb; ++q) {
+                    const unsigned qs = ((U * q) / Gs / (unsigned)KT == r) ? 0u : 1u;
+                    v += scratch[(2 * (size_t)q + qs) * tile_elems + i];
+                }
+                Cs[(i / C::BT) * C::CLD + (i % C::BT)] = v;
+            }
+            if (tid == 0) cnt[r] = 0u;
+            __syncthreads();
+            finish(t, ti, tj);
         }
     }
     if (!group_arrive_last(&st->ticket, G, &flag)) return;
@@ -404,10 +441,8 @@ static hipError_t launch_lp_cfg(const Layout& L, const void* Pin_, void* Pout_, 
         per_cu = nb < 1 ? 1 : nb;
     }
     const int T = L.ldp / C::BT;
-    const int ntiles = T * (T + 1) / 2;
     int G = per_cu * cus;
-    if (G > kMaxPersistent) G = kMaxPersistent;
-    if (G > ntiles) G = ntiles;
+    if (G > L.lp_groups) G = L.lp_groups;   // the workspace holds 2 G partial 128-tiles and G counters
     if (G < 1) G = 1;
     hipLaunchKernelGGL(k_syrk_lp<C>, dim3(G), dim3(C::NT), C::LDS, s, Pin, Pout, L.plane_stride, X,
                        L.ldp, T, st, part, scratch, cnt, step);

@@ -113,3 +113,68 @@ def test_plan_and_learned_argument_checks_without_gpu():
     lib.sp2_learned_density.restype = ctypes.c_int
     assert lib.sp2_learned_density(None, 1, 64, None, None, None, 0, 0, ctypes.c_double(1e-6), None,
                                    None) == -1
+
+
+@pytest.mark.parametrize("k,m,beta,mu,code", [
+    (0, 1, 1.0, 0.0, -1), (65, 1, 1.0, 0.0, -1), (1, 0, 1.0, 0.0, -1), (1, 6, 1.0, 0.0, -1),
+    (4, 9, 1.0, 0.0, -1), (4, 4, 0.0, 0.0, -1), (4, 4, float("inf"), 0.0, -1),
+    (4, 4, 1.0, float("nan"), -1), (4, 4, 1.0, 0.0, -3),
+])
+def test_cheb_argument_checks_without_gpu(k, m, beta, mu, code):
+    """The Chebyshev entry point rejects k outside 1..64, m outside 1..k+4, a
+    non-positive or non-finite beta and a non-finite mu before any HIP call;
+    the last case passes every argument check and fails on the missing
+    workspace."""
+    import paper_2401_13772_amd as sp2
+    lib = ctypes.CDLL(sp2.LIB_PATH)
+    lib.sp2_cheb_density.restype = ctypes.c_int
+    vp = ctypes.c_void_p
+    info = (ctypes.c_char * 128)()
+    assert lib.sp2_cheb_density(vp(1 << 20), vp(1 << 24), 64, 64, 0, ctypes.c_double(mu),
+                                ctypes.c_double(beta), k, m, vp(0), ctypes.c_size_t(0), vp(0),
+                                info) == code
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(G=0), -1), (dict(n=0), -1), (dict(ld=31), -1), (dict(parts=0), -1), (dict(parts=33), -1),
+    (dict(tau=-1.0), -1), (dict(tau=float("nan")), -1), (dict(tau=float("inf")), -1), (dict(dtype=5), -1),
+    (dict(tol=0.0), -1), (dict(max_iter=-1), -1), (dict(max_iter=129), -1),
+])
+def test_graph_argument_checks_without_gpu(kw, code):
+    """sp2_graph_create rejects its arguments before any HIP call; the other
+    graph calls reject a NULL graph."""
+    import paper_2401_13772_amd as sp2
+    lib = ctypes.CDLL(sp2.LIB_PATH)
+    lib.sp2_graph_create.restype = ctypes.c_int
+    a = dict(G=1 << 20, n=32, ld=32, dtype=0, tau=0.1, parts=4, tol=1e-10, max_iter=50)
+    a.update(kw)
+    h = ctypes.c_void_p()
+    vp = ctypes.c_void_p
+    assert lib.sp2_graph_create(ctypes.byref(h), vp(a["G"]), a["n"], a["ld"], a["dtype"],
+                                ctypes.c_double(a["tau"]), a["parts"], ctypes.c_double(a["tol"]),
+                                a["max_iter"], vp(0)) == code
+    assert not h.value
+    assert lib.sp2_graph_parts(None, None, None) == -1
+    assert lib.sp2_graph_nodes(None, 0, None, 0) == -1
+    assert lib.sp2_graph_destroy(None) == -1
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(H=0), -1), (dict(n=0), -1), (dict(n=70000), -1), (dict(ld=3), -1), (dict(n_occ=5), -1),
+    (dict(tol=0.0), -1), (dict(max_iter=129), -1), (dict(dtype=3), -1), (dict(tau=-1.0), -1),
+    (dict(tau=float("nan")), -1), (dict(ws=0), -3), (dict(ws=257), -3), (dict(wsb=16), -3),
+])
+def test_sparse_argument_checks_without_gpu(kw, code):
+    """sp2_density_sparse rejects its arguments before any HIP call."""
+    import paper_2401_13772_amd as sp2
+    lib = ctypes.CDLL(sp2.LIB_PATH)
+    lib.sp2_density_sparse.restype = ctypes.c_int
+    a = dict(H=1 << 20, D=1 << 24, n=4, ld=4, n_occ=2, tol=1e-10, max_iter=50, dtype=0, tau=1e-6,
+             ws=1 << 28, wsb=1 << 30)
+    a.update(kw)
+    vp = ctypes.c_void_p
+    info = (ctypes.c_char * 128)()
+    assert lib.sp2_density_sparse(vp(a["H"]), vp(a["D"]), a["n"], a["ld"], a["n_occ"], ctypes.c_double(a["tol"]),
+                                  a["max_iter"], a["dtype"], ctypes.c_double(a["tau"]), vp(a["ws"]),
+                                  ctypes.c_size_t(a["wsb"]), vp(0), info) == code
+    assert sp2.sp2_sparse_workspace_size(0) == 0 and sp2.sp2_sparse_workspace_size(1000) > 2 * 1024 * 1024 * 8
