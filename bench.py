@@ -592,7 +592,8 @@ def main():
     storage = np.float32 if args.storage == "f32" else np.float64
     log(f"generating tight-binding H n={n} seed={args.seed} gap={args.gap} storage={args.storage}")
     t0 = time.perf_counter()
-    inst = make_tb_hamiltonian(n, args.seed, gap=args.gap, dtype=storage)
+    inst = make_tb_hamiltonian(n, args.seed, gap=args.gap, dtype=storage,
+                               eigh_device="cuda" if n > 8192 else None)
     log(f"  generated in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
     H = torch.from_numpy(inst.H).to(dev)

@@ -59,7 +59,12 @@ struct LpCfg {
     static constexpr int STAGE_BYTES = NP * 2 * PANEL_BYTES;
     static constexpr int CLD = BT + 1;                          // padded row of the LDS S tile (doubles)
     static constexpr size_t CTILE = (size_t)BT * CLD * sizeof(double);
-    static constexpr size_t LDS = 2 * (size_t)STAGE_BYTES > CTILE ? 2 * (size_t)STAGE_BYTES : CTILE;
+    // K slices in flight: as many stages as fit beside nothing else (the S
+    // tile of the epilogue reuses the same LDS), at most 4
+    static constexpr int NS_FIT = (int)((160 * 1024) / STAGE_BYTES);
+    static constexpr int NS = NS_FIT < 4 ? NS_FIT : 4;
+    static_assert(NS >= 2, "two stages at least");
+    static constexpr size_t LDS = (size_t)NS * STAGE_BYTES > CTILE ? (size_t)NS * STAGE_BYTES : CTILE;
     static constexpr int BLOCKS = PANEL_BYTES / 1024;           // 1 KiB LDS-DMA blocks per panel plane
     static constexpr int BPW = BLOCKS / NW;                     // ... per wave
     static_assert(BLOCKS % NW == 0, "panel must split evenly over the waves");
@@ -112,16 +117,37 @@ __device__ __forceinline__ void lp_issue(const typename C::Elem* __restrict__ P,
     }
 }
 
+// Wait until at most N of this wave's vector-memory loads are outstanding
+// (loads complete in issue order, so the older stages are then in LDS).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Stage kt is in LDS once at most `ahead` later stages are outstanding.
+template <class C, bool DIAG>
+__device__ __forceinline__ void lp_wait_stage(int ahead) {
+    constexpr int L = C::NP * (DIAG ? 1 : 2) * C::BPW;   // LDS-DMA loads per stage and wave
+    if (ahead >= 2) wait_vm<2 * L>();
+    else if (ahead == 1) wait_vm<L>();
+    else wait_vm<0>();
+}
+
+// K slices kt0..kt1-1 of tile (ti, tj): C::NS LDS stages, NS - 1 slices
+// loading while one is multiplied.  Each iteration waits for its stage and
+// passes one barrier, after which the stage consumed in the previous
+// iteration is free for the slice NS - 1 ahead.
 template <class C, bool DIAG>
 __device__ __forceinline__ void lp_mainloop(const typename C::Elem* __restrict__ P, size_t pstride, int ldp,
                                             int ti, int tj, int kt0, int kt1, char* smem,
                                             d4 (&acc)[C::MI][C::NI], f4 (&accx)[C::MI][C::NI]) {
+    static_assert(C::NS <= 4, "lp_wait_stage covers up to two stages ahead");
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w / C::WN, wn = w % C::WN;
     const int rowA = ti * C::BT, rowB = tj * C::BT;
-    lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, kt0 * C::KE, smem);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < C::NS - 1; ++s)
+        if (kt0 + s < kt1) lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, (kt0 + s) * C::KE, smem + s * C::STAGE_BYTES);
     // fragment addressing: row r of the wave's sub-tile, chunk c = lane >> 4
     int aoff[C::MI], boff[C::NI];
 #pragma unroll
@@ -135,11 +161,21 @@ __device__ __forceinline__ void lp_mainloop(const typename C::Elem* __restrict__
         boff[ni] = row * 64 + (((lane >> 4) ^ swz(row)) << 4);
     }
     const f4 zero = {0.f, 0.f, 0.f, 0.f};
+    int slot = 0;
     for (int kt = kt0; kt < kt1; ++kt) {
-        const int stg = (kt - kt0) & 1;
-        if (kt + 1 < kt1)
-            lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, (kt + 1) * C::KE, smem + (stg ^ 1) * C::STAGE_BYTES);
-        const char* S = smem + stg * C::STAGE_BYTES;
+        const int ahead = (kt1 - 1 - kt) < (C::NS - 2) ? (kt1 - 1 - kt) : (C::NS - 2);
+        lp_wait_stage<C, DIAG>(ahead);
+        // a bare barrier: __syncthreads() would also wait for the later
+        // stages' loads (its release fence drains every outstanding load)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kt + C::NS - 1 < kt1) {
+            const int ls = (slot + C::NS - 1) % C::NS;
+            lp_issue<C, DIAG>(P, pstride, ldp, rowA, rowB, (kt + C::NS - 1) * C::KE, smem + ls * C::STAGE_BYTES);
+        }
+        const char* S = smem + slot * C::STAGE_BYTES;
+        slot = (slot + 1) % C::NS;
         uint4 af[C::NP][C::MI], bf[C::NP][C::NI];
 #pragma unroll
         for (int p = 0; p < C::NP; ++p) {
@@ -176,9 +212,8 @@ __device__ __forceinline__ void lp_mainloop(const typename C::Elem* __restrict__
                 const f4 t = mfma16<C::MODE>(af[0][mi], bf[0][ni], zero);
                 acc[mi][ni] += d4{(double)t[0], (double)t[1], (double)t[2], (double)t[3]};
             }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
     }
+    __syncthreads();   // every wave is done with the stages before the LDS is reused
 }
 
 // Accumulators -> padded LDS tile S[BT][BT+1] (doubles), S = acc64 + LO_SCALE *

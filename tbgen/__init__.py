@@ -92,20 +92,40 @@ class TBInstance:
 
 
 def make_tb_hamiltonian(n: int, seed: int, gap: float = 0.5, n_occ: int | None = None,
-                        dtype=np.float64) -> TBInstance:
-    """Generate a gapped tight-binding Hamiltonian of size ``n`` (float64 or float32)."""
+                        dtype=np.float64, eigh_device: str | None = None) -> TBInstance:
+    """Generate a gapped tight-binding Hamiltonian of size ``n`` (float64 or float32).
+
+    eigh_device: None = LAPACK on the host; a torch device name ("cuda") =
+    the same FP64 eigendecomposition and rebuild on that device (for large n,
+    where the host takes minutes; the input differs from the host-built one
+    only by rounding)."""
     if n_occ is None:
         n_occ = n // 2
     if not (0 < n_occ < n):
         raise ValueError("0 < n_occ < n required for a gap to open")
     H0 = literal_hamiltonian(n, seed)
-    eps, V = np.linalg.eigh(H0)
+    if eigh_device is None:
+        eps, V = np.linalg.eigh(H0)
+    else:
+        import torch
+        Hd = torch.from_numpy(H0).to(eigh_device)
+        del H0
+        epsd, Vd = torch.linalg.eigh(Hd)
+        del Hd
+        eps = epsd.cpu().numpy()
     gap_lit = float(eps[n_occ] - eps[n_occ - 1])
     shift = max(0.0, gap - gap_lit)
     eps2 = eps.copy()
     eps2[n_occ:] += shift
-    A = (V * eps2) @ V.T
-    H = 0.5 * (A + A.T)
+    if eigh_device is None:
+        A = (V * eps2) @ V.T
+        H = 0.5 * (A + A.T)
+    else:
+        e2 = torch.from_numpy(eps2).to(eigh_device)
+        A = (Vd * e2) @ Vd.T
+        del Vd
+        H = (0.5 * (A + A.T)).cpu().numpy()
+        del A
     H = np.ascontiguousarray(H.astype(dtype))
     return TBInstance(H, n_occ, gap, gap_lit, shift, eps2)
 
