@@ -549,7 +549,7 @@ def main():
     ap.add_argument("--sparse-tau", type=float, default=1e-5, help="sparse workload: drop threshold")
     ap.add_argument("--layers", type=int, default=16, help="learned workload: quadratic layers")
     ap.add_argument("--train", type=int, default=20000, help="learned workload: training Hamiltonians")
-    ap.add_argument("--epochs", type=int, default=60, help="learned workload: passes over the training set")
+    ap.add_argument("--epochs", type=int, default=600, help="learned workload: passes over the training set")
     ap.add_argument("--batch-learned", type=int, default=256, help="learned workload: held-out batch")
     ap.add_argument("--batch-max-iter", type=int, default=60)
     ap.add_argument("--autotune-cache", default="",

@@ -128,7 +128,8 @@ size_t sp2_workspace_size(int n, sp2_dtype dtype, sp2_compute compute);
  *                    spectrum and rounding errors would be amplified;
  *                 2. trace-steered steps with split-operand 16-bit products
  *                    and FP32 accumulation (traces and norms in FP64) until
- *                    the idempotency stops decreasing;
+ *                    the idempotency stops decreasing over two steps from a
+ *                    value below 0.1;
  *                 3. FP64 refinement steps alternating X^2 and 2X - X^2
  *                    (not steered by the trace) until e <= tol, at most 8.
  *               info->fp64_prefix_iters and info->refine_steps report 1 and 3.
@@ -313,12 +314,17 @@ int sp2_graph_destroy(sp2_graph* graph);
  *   the trained layers, then an SP2 check step on their output X_L.  If
  *   ||X_L^2 - X_L||_F <= idem_fallback and the trace error is within
  *   idem_fallback, D is the check step's output (status SP2_OK).  Else, if
- *   ||X_L^2 - X_L||_F <= 0.25 (every eigenvalue within (-0.21, 1.21)), plain
+ *   ||X_L^2 - X_L||_F <= 0.3 (every eigenvalue within [-0.242, 1.242]), one
+ *   step of the branch the check step did not take pulls the spectrum into
+ *   [0, 1] without moving any eigenvalue across the middle, and plain
  *   trace-steered SP2 steps continue on the device with sp2_density's stop
- *   rule (tol 1e-10), up to 60 of them.  Else the matrix is solved again from H
- *   by plain FP64 SP2 and reported as SP2_E_FALLBACK.  info.fp64_prefix_iters
- *   = the learned layers applied, info.refine_steps = the plain SP2 steps
- *   after them (or of the solve from H), info.iterations = all squarings.
+ *   rule (tol 1e-10), up to 60 of them.  Else the matrix restarts plain FP64
+ *   SP2 from its X_0 (kept by the plan) within the same run, and if that or
+ *   the continuation does not converge it is solved again from H by
+ *   sp2_density; both are reported as SP2_E_FALLBACK.  info.fp64_prefix_iters
+ *   = the learned layers applied, info.refine_steps = the steps after the
+ *   check step (the continuation's, or the plain SP2 solve's), info.iterations
+ *   = all squarings.
  *   compute: SP2_C_F64 (others SP2_E_UNSUPPORTED).  The model keeps an
  *   inference plan for the last (batch, n, n_occ, dtype, bar) and a
  *   workspace for the fallback solves; calls on one model must not overlap.

@@ -31,6 +31,26 @@ struct PairLds<float> {
 template <typename T, typename L>
 __device__ inline void load_pair(const T* __restrict__ H, int n, int ld, int I, int J,
                                  L (*sA)[kBndTile + 1], L (*sB)[kBndTile + 1], int& bad) {
+    constexpr int V = 16 / (int)sizeof(T);     // elements per 16-byte load
+    constexpr int VPR = kBndTile / V;          // loads per tile row
+    typedef T vec __attribute__((ext_vector_type(V)));
+    const bool whole = (I + 1) * kBndTile <= n && (J + 1) * kBndTile <= n && (ld % V) == 0 &&
+                       (reinterpret_cast<uintptr_t>(H) % 16) == 0;
+    if (whole) {
+        // interior pair: 16-byte loads, the same values as the element loop
+        for (int e = threadIdx.x; e < kBndTile * VPR; e += kThreads) {
+            const int rr = e / VPR, cv = (e % VPR) * V;
+            const vec a = *(const vec*)(H + (size_t)(I * kBndTile + rr) * ld + J * kBndTile + cv);
+            const vec b = *(const vec*)(H + (size_t)(J * kBndTile + rr) * ld + I * kBndTile + cv);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                bad |= !isfinite((double)a[v]) | !isfinite((double)b[v]);
+                sA[rr][cv + v] = (L)a[v];
+                sB[rr][cv + v] = (L)b[v];
+            }
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < kBndTile * kBndTile; e += kThreads) {
         const int rr = e >> 6, cc = e & 63;
         const int ra = I * kBndTile + rr, ca = J * kBndTile + cc;

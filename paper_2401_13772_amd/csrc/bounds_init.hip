@@ -56,8 +56,18 @@ __global__ __launch_bounds__(kThreads) void k_bounds_final(const T* __restrict__
     const int i = blockIdx.x * kThreads + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
     if (i < n) {
+        // R_i = the column-tile partials added in tile order; eight loads in
+        // flight at a time (the sum's order is unchanged)
         double R = 0.0;
-        for (int K = 0; K < nb; ++K) R += rowpart[(size_t)K * ldp + i];
+        int K = 0;
+        for (; K + 8 <= nb; K += 8) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = rowpart[(size_t)(K + q) * ldp + i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) R += v[q];
+        }
+        for (; K < nb; ++K) R += rowpart[(size_t)K * ldp + i];
         const double c = (double)H[(size_t)i * ld + i];
         lo = c - R;
         hi = c + R;

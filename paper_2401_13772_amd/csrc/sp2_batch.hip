@@ -50,6 +50,7 @@ struct BatchMat {
     void* D;
     double* x0;
     double* x1;
+    double* xk;        // learned plans: a kept copy of X_0 for the in-run restart (else null)
     double* part;
     double* rowpart;   // Gershgorin row partials, (ldp / 64) x ldp
     State* st;
@@ -67,7 +68,10 @@ __global__ void k_batch_reset(BatchMat* mats, int batch, double tol, int max_ite
     if (b >= batch) return;
     if (mats[b].mu_mode) state_reset_mu(mats[b].st, mats[b].n, mats[b].mu, tol, max_iter);
     else if (n_layers < 0) state_reset(mats[b].st, mats[b].n, mats[b].n_occ, tol, max_iter, 0);
-    else state_reset_learned(mats[b].st, mats[b].n, mats[b].n_occ, tol, max_iter, n_layers, idem_fallback);
+    else {
+        state_reset_learned(mats[b].st, mats[b].n, mats[b].n_occ, tol, max_iter, n_layers, idem_fallback);
+        if (mats[b].xk) mats[b].st->restart_step = -2;   // a rejected check restarts SP2 from X_0
+    }
 }
 
 template <typename T>
@@ -136,6 +140,12 @@ __global__ __launch_bounds__(kThreads) void k_batch_bounds_init(const BatchMat* 
         __syncthreads();
         pair_x0(n, ldp, I, J, emax, width, sA, sB, sA, M.x0, bred, M.part, p);
     }
+    if (M.xk) {
+        // keep X_0 for a restart after rejected learned layers
+        __syncthreads();
+        const size_t q = (size_t)ldp * ldp / 4;
+        for (size_t i = tid; i < q; i += kThreads) ((d4*)M.xk)[i] = ((const d4*)M.x0)[i];
+    }
     __threadfence();
     __syncthreads();
     double t = 0.0, f = 0.0;
@@ -166,7 +176,7 @@ __global__ __launch_bounds__(C::NT) void k_batch_step(const BatchMat* __restrict
     if (st->done || st->iterations != step || st->phase == 1) return;
     const int grow = st->grow;
     const int ldp = M.ldp;
-    const double* X = (step & 1) ? M.x1 : M.x0;
+    const double* X = (st->restart_step == step) ? M.xk : ((step & 1) ? M.x1 : M.x0);
     double* Y = (step & 1) ? M.x0 : M.x1;
     const int T = ldp / C::BT;
     const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
@@ -238,7 +248,9 @@ __global__ void k_batch_info(const BatchMat* __restrict__ mats, int batch, sp2_i
     if (b >= batch) return;
     const State* st = mats[b].st;
     sp2_info r;
-    r.status = st->status;
+    // a solve restarted from X_0 after rejected learned layers is reported
+    // as a fallback (its D is that of the plain SP2 solve)
+    r.status = (st->restarted && st->status == SP2_OK) ? SP2_E_FALLBACK : st->status;
     r.iterations = st->iterations;
     r.fp64_prefix_iters = st->fp64_steps;
     r.refine_steps = st->refine_steps;
@@ -515,9 +527,10 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
         off_rp[k] = off;
         off = up256(off + (size_t)(ldp[k] / kBndTile) * ldp[k] * sizeof(double));
     }
+    const int nbuf = n_layers >= 0 ? 3 : 2;   // learned plans keep X_0 too
     for (int k = 0; k < batch; ++k) {
         off_x[k] = off;
-        off = up256(off + 2 * (size_t)ldp[k] * ldp[k] * sizeof(double));
+        off = up256(off + nbuf * (size_t)ldp[k] * ldp[k] * sizeof(double));
     }
     if (hipMalloc(&p->dmem, off) != hipSuccess ||
         hipHostMalloc((void**)&p->h_mats, batch * sizeof(BatchMat), hipHostMallocDefault) != hipSuccess ||
@@ -540,6 +553,7 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
         m.rowpart = (double*)(base + off_rp[k]);
         m.x0 = (double*)(base + off_x[k]);
         m.x1 = m.x0 + (size_t)ldp[k] * ldp[k];
+        m.xk = n_layers >= 0 ? m.x1 + (size_t)ldp[k] * ldp[k] : nullptr;
         m.n = n[p->order[k]];
         m.ldp = ldp[k];
         m.n_occ = mu_mode ? 0 : n_occ[p->order[k]];

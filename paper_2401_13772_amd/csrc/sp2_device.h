@@ -223,6 +223,9 @@ __device__ inline void state_reset(State* st, int n, int n_occ, double tol, int 
     st->xmu = 0.0;
     st->sp_slices = 0ull;
     st->sp_tiles = 0ull;
+    st->restart_step = -1;
+    st->restarted = 0;
+    st->tr0 = 0.0;
 }
 
 // Start of a solve steered by a chemical potential mu (one thread): the
@@ -267,6 +270,7 @@ __device__ inline void learned_update_coefs(const double* abc, int grow, double&
 // max_iter == 0 end the solve before the first squaring.
 __device__ inline void state_after_init(State* st, double t, double f) {
     st->tr = t;
+    st->tr0 = t;
     st->fro2 = f;
     st->grow = (t - st->nocc <= 0.0) ? 1 : 0;
     const int nn = st->n;
@@ -352,7 +356,8 @@ __device__ __forceinline__ void sp2_steer_thread0(State* st, double E, double TR
     }
     const int phase = st->phase;
     if (phase == 0) {
-        st->fp64_steps = st->fp64_steps + 1;
+        if (st->restarted) st->refine_steps = st->refine_steps + 1;   // SP2 from X_0 after the layers
+        else st->fp64_steps = st->fp64_steps + 1;
         st->grow = trace_grow;
         // stagnation: no progress over two steps once every eigenvalue is
         // near 0 or 1.  Steered by mu, the branch follows mu's image, which
@@ -365,7 +370,8 @@ __device__ __forceinline__ void sp2_steer_thread0(State* st, double E, double TR
         if (e <= st->tol) {
             st->done = 1;
             st->status = SP2_OK;
-        } else if (m >= stag_span && e >= st->e_hist[m - stag_span] && e < stag_below) {
+        } else if (m >= stag_span && m - stag_span >= st->restart_step &&
+                   e >= st->e_hist[m - stag_span] && e < stag_below) {
             st->done = 1;
             st->status = SP2_E_STAGNATED;
         } else if (m + 1 >= st->max_iter) {
@@ -379,7 +385,11 @@ __device__ __forceinline__ void sp2_steer_thread0(State* st, double E, double TR
         st->lp_mask[m >> 6] |= 1ull << (m & 63);
         st->lp_steps = st->lp_steps + 1;
         st->grow = trace_grow;
-        const bool floor_hit = (m - st->lp_start >= 2) && e >= st->e_hist[m - 2] && e < 0.1;
+        // the rounding floor: no progress over two steps from below 0.1.  The
+        // earlier value decides, so that a run-away from the floor (FP8 at
+        // n = 16384: e = 0.087, 0.154, 0.302, 0.6, ... as levels just outside
+        // [0, 1] are squared) hands over as well
+        const bool floor_hit = (m - st->lp_start >= 2) && e >= st->e_hist[m - 2] && st->e_hist[m - 2] < 0.1;
         if (e <= st->tol) {
             st->done = 1;
             st->status = SP2_OK;
@@ -403,21 +413,42 @@ __device__ __forceinline__ void sp2_steer_thread0(State* st, double E, double TR
             st->phase = 4;
         }
     } else if (phase == 4) {
-        // the SP2 check step: e is the idempotency of the last layer's output.
-        // Accepted: done.  Close to a projector (every eigenvalue x has
-        // |x^2 - x| <= 0.25, so x lies in (-0.21, 1.21), where trace-steered
-        // SP2 steps pull it to 0 or 1): plain SP2 steps go on from here.
+        // the SP2 check step: e is the idempotency of the last layer's output
+        // X_L.  Accepted: done.  Close to a projector (e <= 0.3 bounds every
+        // eigenvalue's |x^2 - x|, so x lies in [-0.242, 1.242]): one step of
+        // the other branch pulls the check step's output into [0, 1] on the
+        // same side of the middle (x^2 of [-0.242, 1.242] is [0, 1.542], and
+        // 2y - y^2 of that is [0, 1] with 1.542 -> 0.707; 2x - x^2 gives
+        // [-0.542, 1], and y^2 of that [0, 1] with -0.542 -> 0.293), after
+        // which trace-steered SP2 steps are safe (they keep [0, 1]).
         // Otherwise the solve stops for a restart from H (SP2_E_FALLBACK).
-        st->grow = trace_grow;
         const double terr = fabs(TR - st->nocc);
         if (e <= st->idem_fallback && terr <= st->idem_fallback) {
+            st->grow = trace_grow;
             st->done = 1;
             st->status = SP2_OK;
-        } else if (e <= 0.25 && m + 1 < st->max_iter) {
-            st->phase = 5;
+        } else if (e <= 0.3 && m + 2 < st->max_iter) {
+            st->phase = 6;
+            st->grow = grow ? 0 : 1;
+        } else if (st->restart_step == -2 && m + 2 < st->max_iter) {
+            // the plan keeps a copy of X_0: plain SP2 from it, in this run
+            st->restart_step = m + 1;
+            st->restarted = 1;
+            st->phase = 0;
+            st->tr = st->tr0;
+            st->grow = (st->tr0 - st->nocc <= 0.0) ? 1 : 0;
         } else {
             st->done = 1;
             st->status = SP2_E_FALLBACK;
+        }
+    } else if (phase == 6) {
+        // the pull-in step after the check: plain SP2 from here
+        st->refine_steps = st->refine_steps + 1;
+        st->phase = 5;
+        st->grow = trace_grow;
+        if (e <= st->tol) {
+            st->done = 1;
+            st->status = SP2_OK;
         }
     } else if (phase == 5) {
         // plain SP2 after the learned layers (the stop rule of phase 0)

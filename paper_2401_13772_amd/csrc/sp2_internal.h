@@ -53,6 +53,11 @@ struct State {
     int32_t pad2;
     double mu;
     double xmu;
+    // learned expansion: restart from X_0 inside the plan after a rejected
+    // check (restart_step: the step that reads the kept copy of X_0; -1 none)
+    int32_t restart_step;
+    int32_t restarted;
+    double tr0;         // trace of X_0
     // thresholded SP2: K slices multiplied and output tiles computed, summed
     // over the steps of the solve
     unsigned long long sp_slices;

@@ -377,7 +377,11 @@ int sp2_learned_density(sp2_learned* model, int batch, int n, const void* const*
     // plain SP2 from H for every rejected matrix
     int worst_neg = 0, worst_pos = SP2_OK;
     for (int b = 0; b < batch; ++b) {
-        if (inf[b].status == SP2_E_FALLBACK) {
+        // a continuation or in-run restart that did not converge, or a
+        // rejection the run could not restart (refine_steps == 0): solve
+        // again from H on the host side of the plan
+        if ((inf[b].status == SP2_E_FALLBACK && inf[b].refine_steps == 0) ||
+            inf[b].status == SP2_E_NOT_CONVERGED || inf[b].status == SP2_E_STAGNATED) {
             const size_t need = sp2_workspace_size(n, dtype, SP2_C_F64);
             if (model->fb_ws_bytes < need) {
                 if (model->fb_ws) (void)hipFree(model->fb_ws);
