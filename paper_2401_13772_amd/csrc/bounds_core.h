@@ -44,7 +44,7 @@ __device__ inline void load_pair(const T* __restrict__ H, int n, int ld, int I, 
             const vec b = *(const vec*)(H + (size_t)(J * kBndTile + rr) * ld + I * kBndTile + cv);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                bad |= !isfinite((double)a[v]) | !isfinite((double)b[v]);
+                bad |= (int)!isfinite((double)a[v]) | (int)!isfinite((double)b[v]);
                 sA[rr][cv + v] = (L)a[v];
                 sB[rr][cv + v] = (L)b[v];
             }
@@ -57,7 +57,7 @@ __device__ inline void load_pair(const T* __restrict__ H, int n, int ld, int I, 
         const int rb = J * kBndTile + rr, cb = I * kBndTile + cc;
         const T a = (ra < n && ca < n) ? H[(size_t)ra * ld + ca] : T(0);
         const T b = (rb < n && cb < n) ? H[(size_t)rb * ld + cb] : T(0);
-        bad |= !isfinite((double)a) | !isfinite((double)b);
+        bad |= (int)!isfinite((double)a) | (int)!isfinite((double)b);
         sA[rr][cc] = (L)a;
         sB[rr][cc] = (L)b;
     }

@@ -47,7 +47,7 @@ __device__ inline double group_sum(double v, double* scratch) {
 
 // True in every thread of the one workgroup that arrives last.
 __device__ inline bool group_arrive_last(unsigned* ticket, unsigned nblocks, int* flag_lds) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned t = atomicAdd(ticket, 1u);
@@ -55,7 +55,7 @@ __device__ inline bool group_arrive_last(unsigned* ticket, unsigned nblocks, int
     }
     __syncthreads();
     bool last = *flag_lds != 0;
-    if (last) __threadfence();
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return last;
 }
 
@@ -75,6 +75,21 @@ __device__ inline bool group_arrive_last(unsigned* ticket, unsigned nblocks, int
 
 template <int MODE> struct Planes;
 
+// FP16 nearest-even rounding of a double in a few instructions: round to FP32
+// first, then force the FP32 value to round-to-odd (truncate toward zero and
+// set the last bit when the first rounding was inexact).  24 >= 11 + 2 bits,
+// so the second rounding to FP16 is then the correctly rounded result of x
+// (Boldo & Melquiond, rounding to odd, IEEE Trans. Computers 2008); the plain
+// (_Float16)x conversion has no instruction on gfx950 and becomes ~40 integer
+// instructions.  NaN and infinity pass through.
+__device__ inline _Float16 f64_to_f16_rn(double x) {
+    const float f = (float)x;
+    const double fd = (double)f;
+    unsigned b = __float_as_uint(f);
+    if (fd != x) b = (fabs(fd) > fabs(x) ? b - 1u : b) | 1u;
+    return (_Float16)__uint_as_float(b);
+}
+
 template <> struct Planes<SP2_C_F16X2> {
     static constexpr int NP = 2;
     static constexpr double HI_SCALE = 1.0;
@@ -82,8 +97,8 @@ template <> struct Planes<SP2_C_F16X2> {
     typedef uint16_t Elem;
     typedef _Float16 T;
     __device__ static inline void encode(double x, uint16_t* out) {
-        const _Float16 h = (_Float16)x;
-        const _Float16 l = (_Float16)((x - (double)h) * 2048.0);
+        const _Float16 h = f64_to_f16_rn(x);
+        const _Float16 l = f64_to_f16_rn((x - (double)h) * 2048.0);
         out[0] = __builtin_bit_cast(uint16_t, h);
         out[1] = __builtin_bit_cast(uint16_t, l);
     }

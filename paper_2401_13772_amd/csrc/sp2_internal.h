@@ -82,6 +82,7 @@ struct Layout {
 };
 
 constexpr int kLpTile = 128;  // tile edge of the split-operand kernels
+constexpr int kFixRows = 8;   // S rows per workgroup of a step's finishing kernel (k_sk_finish)
 
 inline int planes_of(sp2_compute c) {
     return c == SP2_C_F16X2 ? 2 : c == SP2_C_BF16X3 ? 3 : c == SP2_C_BF16X2 ? 2 : c == SP2_C_FP8 ? 2 : 0;
@@ -106,13 +107,19 @@ inline Layout make_layout(int n, sp2_compute compute) {
     int T = L.ldp / L.bt;
     L.tiles = T * (T + 1) / 2;
     int nb = L.ldp / kBndTile;
-    size_t part_entries = (size_t)L.tiles * 4;
-    size_t init_entries = (size_t)nb * nb * 4;
-    if (init_entries > part_entries) part_entries = init_entries;
     const int nbt = L.ldp / kBndTile;   // 64-row tiles of the bounds / X_0 kernels
     // the 128-tile FP64 kernel runs up to kMaxPersistent workgroups whatever
     // the tile count (its stream-K remainder spreads a few tiles over many)
     L.max_groups = (L.bt == 128 || L.tiles > kMaxPersistent) ? kMaxPersistent : L.tiles;
+    // per-tile sums: the whole tiles, plus one entry per kFixRows-row block of
+    // each split tile of a 128-tile step (fewer split tiles than workgroups)
+    const int Tl128 = L.ldp / kLpTile;
+    const int tiles128 = Tl128 * (Tl128 + 1) / 2;
+    size_t part_entries = (size_t)(L.tiles > tiles128 ? L.tiles : tiles128) +
+                          (size_t)(kLpTile / kFixRows - 1) * kMaxPersistent;
+    part_entries *= 4;
+    size_t init_entries = (size_t)nb * nb * 4;
+    if (init_entries > part_entries) part_entries = init_entries;
     size_t off = 0;
     L.off_state = off;   off = align_up(off + sizeof(State), 256);
     L.off_part = off;    off = align_up(off + part_entries * sizeof(double), 256);
@@ -173,7 +180,7 @@ __device__ inline double block_sum(double v, double* scratch) {
 // Returns true in every thread of the single block that arrives last; that
 // block then sees all other blocks' partials.
 __device__ inline bool arrive_last(State* st, unsigned nblocks, int* flag_lds) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned t = atomicAdd(&st->ticket, 1u);
@@ -181,7 +188,7 @@ __device__ inline bool arrive_last(State* st, unsigned nblocks, int* flag_lds) {
     }
     __syncthreads();
     bool last = *flag_lds != 0;
-    if (last) __threadfence();
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return last;
 }
 

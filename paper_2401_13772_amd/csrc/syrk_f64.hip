@@ -32,7 +32,7 @@
 //     in that XCD's L2;
 //   * per-tile sums go to a partial buffer that the last-arriving workgroup
 //     adds in tile order: deterministic, no floating-point atomics.
-#include "syrk_f64_core.h"
+#include "sk_finish.h"
 
 namespace sp2 {
 
@@ -93,12 +93,12 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64(const double* __restrict__ X
             for (int mi = 0; mi < C::MI; ++mi)
 #pragma unroll
                 for (int ni = 0; ni < C::NI; ++ni) mine[(mi * C::NI + ni) * C::NT + tid] = acc[mi][ni];
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             if (tid == 0) flag = (int)atomicAdd(&cnt[bidx], 1u);
             __syncthreads();
             if (flag == 0) continue;             // the other segment will finish the tile
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
             for (int mi = 0; mi < C::MI; ++mi)
 #pragma unroll
@@ -142,19 +142,20 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64(const double* __restrict__ X
 // The R = N mod G tiles left over are split evenly over all G workgroups as
 // contiguous ranges of K slices (a range is shorter than a tile, so it touches
 // at most two tiles).  Each segment of a split tile is stored as an FP64
-// partial in slot 2g (the workgroup's first tile) or 2g + 1 (its second); the
-// last of the tile's segments to arrive adds all of them in workgroup order
-// and runs the epilogue.  The sum does not depend on arrival order.
+// partial in slot 2g (the workgroup's first tile) or 2g + 1 (its second).
+// The step's second kernel, k_sk_finish, adds a split tile's partials in
+// workgroup order (the sum does not depend on which segment finished last),
+// runs the split tiles' epilogue and takes the steering decision: this kernel
+// needs no fence or counter between its workgroups.  The remainder runs
+// before the waves, so its partial stores do not trail the waves.
 constexpr int kGroupM = 8;
 
 template <class C>
 __global__ __launch_bounds__(C::NT) void k_syrk_f64_hyb(const double* __restrict__ X, double* __restrict__ Y,
                                                         int ldp, int T, State* st, double* __restrict__ part,
-                                                        double* __restrict__ scratch,
-                                                        unsigned* __restrict__ cnt, int step) {
+                                                        double* __restrict__ scratch, int step) {
     extern __shared__ __attribute__((aligned(16))) char lsm[];
     __shared__ double red[C::NW];
-    __shared__ int flag;
 
     if (st->done || st->iterations != step || st->phase == 1) return;
     const int grow = st->grow;
@@ -180,6 +181,51 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64_hyb(const double* __restrict
         }
     };
 
+    // stream-K remainder (the split of SkSplit): each segment of a split tile
+    // leaves its FP64 partial tile, row-major, in slot 2g (the range's first
+    // tile) or 2g + 1; k_sk_finish adds them after this kernel.  R < G <= 1024
+    // and KT <= 4096 keep every product below 2^32 (32-bit range arithmetic).
+    if (R > 0) {
+        const SkSplit sk(R, (unsigned)KT, G);
+        // remainder owners by hardware block index: blocks are dealt round-robin
+        // to the XCDs, so the owners spread over all of them
+        const unsigned gr = blockIdx.x;
+        unsigned u, u1;
+        sk.range(gr, u, u1);
+        int seg_no = 0;
+        const int lane = tid & 63, w = tid >> 6;
+        const int wm = w / C::WN, wn = w % C::WN;
+        while (u < u1) {
+            const unsigned r = u / (unsigned)KT;
+            const int k0 = (int)(u - r * (unsigned)KT);
+            const unsigned kend = (unsigned)k0 + (u1 - u);
+            const int k1 = kend < (unsigned)KT ? (int)kend : KT;
+            int ti, tj;
+            grouped_tile(Dt + r, T, kGroupM, ti, tj);
+            d4 acc[C::MI][C::NI];
+#pragma unroll
+            for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+            if (ti == tj) syrk_mainloop_dma<C, true>(X, ldp, ti, tj, k0, k1, lsm, acc);
+            else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, k0, k1, lsm, acc);
+            u += (unsigned)(k1 - k0);
+            double* mine = scratch + (2 * (size_t)gr + seg_no++) * (size_t)C::BT * C::BT;
+            // accumulator (mi, ni, r) of a lane: row 16 mi + lane / 16 + 4 r of
+            // the wave's sub-tile, column 16 ni + lane % 16
+#pragma unroll
+            for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < C::NI; ++ni)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = wm * C::WTM + mi * 16 + (lane >> 4) + 4 * q;
+                        const int col = wn * C::WTN + ni * 16 + (lane & 15);
+                        mine[row * C::BT + col] = acc[mi][ni][q];
+                    }
+        }
+    }
+
     // data-parallel waves
     for (unsigned w = 0; w < waves; ++w) {
         const unsigned t = w * G + g;
@@ -194,89 +240,6 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64_hyb(const double* __restrict
         else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, 0, KT, lsm, acc);
         finish(t, ti, tj, acc);
     }
-
-    // stream-K remainder: the R * KT remainder slices over the first Gs
-    // workgroups, every range non-empty and at least KT/16 long (a tile has
-    // at most 16 segments to add).  R < G <= 1024 and KT <= 4096 keep every
-    // product below 2^32, so the range arithmetic is 32-bit.
-    if (R > 0) {
-        const unsigned U = R * (unsigned)KT;
-        const unsigned minr = KT >= 16 ? (unsigned)KT / 16u : 1u;
-        const unsigned Gs = (U / minr < G) ? (U / minr > 0 ? U / minr : 1u) : G;
-        // remainder owners by hardware block index: blocks are dealt round-robin
-        // to the XCDs, so the Gs owners spread over all of them
-        const unsigned gr = blockIdx.x;
-        const unsigned u0 = gr < Gs ? (U * gr) / Gs : U;
-        const unsigned u1 = gr < Gs ? (U * (gr + 1)) / Gs : U;
-        unsigned u = u0;
-        int seg_no = 0;
-        while (u < u1) {
-            const unsigned r = u / (unsigned)KT;
-            const int k0 = (int)(u - r * (unsigned)KT);
-            const unsigned kend = (unsigned)k0 + (u1 - u);
-            const int k1 = kend < (unsigned)KT ? (int)kend : KT;
-            const unsigned t = Dt + r;
-            int ti, tj;
-            grouped_tile(t, T, kGroupM, ti, tj);
-            d4 acc[C::MI][C::NI];
-#pragma unroll
-            for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
-            if (ti == tj) syrk_mainloop_dma<C, true>(X, ldp, ti, tj, k0, k1, lsm, acc);
-            else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, k0, k1, lsm, acc);
-            u += (unsigned)(k1 - k0);
-            const int slot = seg_no++;
-            if (k0 == 0 && k1 == KT) {        // a whole tile in one range
-                finish(t, ti, tj, acc);
-                continue;
-            }
-            // owners of the tile's first and last slice: the workgroups q
-            // with (U q)/Gs <= s < (U (q + 1))/Gs
-            const unsigned ts = r * (unsigned)KT, te = ts + (unsigned)KT;
-            const unsigned ga = ((ts + 1) * Gs - 1) / U;
-            const unsigned gb = (te * Gs - 1) / U;
-            const size_t tile_elems = (size_t)C::BT * C::BT;
-            d4* mine = (d4*)(scratch + (2 * (size_t)gr + slot) * tile_elems);
-#pragma unroll
-            for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < C::NI; ++ni) mine[(mi * C::NI + ni) * C::NT + tid] = acc[mi][ni];
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) flag = (int)atomicAdd(&cnt[r], 1u);
-            __syncthreads();
-            if (flag != (int)(gb - ga)) continue;    // not the last segment to arrive
-            __threadfence();
-#pragma unroll
-            for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
-            for (unsigned q = ga; q <= gb; ++q) {
-                // tile r is q's first tile unless q's range starts in an earlier tile
-                const unsigned qs = ((U * q) / Gs / (unsigned)KT == r) ? 0u : 1u;
-                const d4* o = (const d4*)(scratch + (2 * (size_t)q + qs) * tile_elems);
-#pragma unroll
-                for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] += o[(mi * C::NI + ni) * C::NT + tid];
-            }
-            if (tid == 0) cnt[r] = 0u;
-            finish(t, ti, tj, acc);
-        }
-    }
-
-    if (!group_arrive_last(&st->ticket, G, &flag)) return;
-    double E = 0.0, TR = 0.0, F = 0.0;
-    for (unsigned k = tid; k < ntiles; k += C::NT) {
-        E += part[4 * k + 0];
-        TR += part[4 * k + 1];
-        F += part[4 * k + 2];
-    }
-    E = group_sum<C::NW>(E, red);
-    TR = group_sum<C::NW>(TR, red);
-    F = group_sum<C::NW>(F, red);
-    if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
 }
 
 using CfgHyb = SyrkCfg<128, 2, 2>;   // 256 threads, 64 x 64 per wave, LDS-DMA operands
@@ -304,8 +267,9 @@ static hipError_t launch_hyb(const Layout& L, const double* X, double* Y, State*
     int G = per_cu * cus;
     if (G > L.max_groups) G = L.max_groups;   // the workspace holds 2 G partial tiles and G counters
     if (G < 1) G = 1;
-    hipLaunchKernelGGL(k_syrk_f64_hyb<C>, dim3(G), dim3(C::NT), lds, s, X, Y, L.ldp, T, st, part, scratch, cnt,
-                       step);
+    hipLaunchKernelGGL(k_syrk_f64_hyb<C>, dim3(G), dim3(C::NT), lds, s, X, Y, L.ldp, T, st, part, scratch, step);
+    hipLaunchKernelGGL((k_sk_finish<C::BT, F64IO, false>), dim3(sk_finish_grid(T * (T + 1) / 2, G, C::BT)),
+                       dim3(kFixThreads), 0, s, F64IO{X, Y}, L.ldp, T, kBK, st, part, scratch, (unsigned)G, step);
     return hipGetLastError();
 }
 

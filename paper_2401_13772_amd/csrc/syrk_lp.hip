@@ -17,8 +17,8 @@
 // FP64 step (Section "SP2 solver": X' = X^2 or 2X - X^2 by the trace),
 // evaluated in FP64 from the decoded X and S; it writes the planes of X'
 // (they are the iterate during this phase: no FP64 copy is stored) and the
-// per-tile e^2, trace and ||X'||^2.  Steering is taken by the last-arriving
-// workgroup (sp2_steer_thread0).
+// per-tile e^2, trace and ||X'||^2.  The step's second kernel, k_sk_finish,
+// completes the split tiles and steers (sp2_steer_thread0).
 //
 // Design for CDNA4:
 //   * 128 x 128 tiles of the lower block triangle, 8 wave64s each owning
@@ -29,12 +29,13 @@
 //     wave instruction fills 1 KiB = 16 rows x 64 B; a row's four 16-byte
 //     chunks are stored XOR-swizzled by (row >> 1) & 3 so that the eight lanes
 //     a ds_read_b128 serves per cycle hit distinct banks;
-//   * double-buffered K slices of 32 elements, one barrier per slice;
+//   * up to four K slices of 32 elements in LDS (three loading while one is
+//     multiplied), one barrier per slice;
 //   * the schedule of the 128-tile FP64 step: grouped raster, K-synchronous
 //     data-parallel waves (the workgroups of one XCD share panels in L2) and
-//     a stream-K remainder with an order-independent fix-up of FP64 partial
-//     tiles.
-#include "syrk_f64_core.h"
+//     a stream-K remainder whose FP64 partial tiles k_sk_finish adds in a
+//     fixed order.
+#include "sk_finish.h"
 
 namespace sp2 {
 
@@ -246,7 +247,9 @@ __device__ __forceinline__ void lp_acc_to_lds(const d4 (&acc)[C::MI][C::NI], con
 //   pass B (off-diagonal tiles): the mirrored tile (rows of tj), from the
 //           transposed LDS tile and X read at the mirrored place (the planes
 //           are bitwise symmetric, so X' comes out bit-identical).
-// Diagonal tiles take the lower triangle's S for both halves.
+// Diagonal tiles take the lower triangle's S for both halves.  All plane
+// loads of a pass are issued before the first is used, so a pass pays one
+// memory latency rather than one per run.
 template <class C>
 __device__ __forceinline__ void lp_epilogue(const typename C::Elem* __restrict__ Pin,
                                             typename C::Elem* __restrict__ Pout,
@@ -254,34 +257,48 @@ __device__ __forceinline__ void lp_epilogue(const typename C::Elem* __restrict__
                                             const double* Cs, double& e2, double& trp, double& fro) {
     constexpr int RUN = 8;
     constexpr int RUNS_PER_ROW = C::BT / RUN;
+    constexpr int RPT = C::BT * RUNS_PER_ROW / C::NT;   // runs per thread and pass
+    static_assert(C::BT * RUNS_PER_ROW % C::NT == 0, "runs must split evenly over the threads");
     const bool diag = (ti == tj);
     typedef typename C::Elem E;
     typedef E u16x8 __attribute__((ext_vector_type(8)));
+    const double wgt = diag ? 1.0 : 2.0;
+#pragma unroll 1
     for (int pass = 0; pass < (diag ? 1 : 2); ++pass) {
-        const int rbase = (pass == 0 ? ti : tj) * C::BT;
-        const int cbase = (pass == 0 ? tj : ti) * C::BT;
-        for (int q = threadIdx.x; q < C::BT * RUNS_PER_ROW; q += C::NT) {
+        const bool mirrored = pass == 1;
+        const int rbase = (mirrored ? tj : ti) * C::BT;
+        const int cbase = (mirrored ? ti : tj) * C::BT;
+        u16x8 xin[RPT][C::NP];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int q = threadIdx.x + j * C::NT;
             const int r = q / RUNS_PER_ROW, c0 = (q % RUNS_PER_ROW) * RUN;
             const size_t g = (size_t)(rbase + r) * ldp + cbase + c0;
-            u16x8 xin[C::NP], xout[C::NP];
 #pragma unroll
-            for (int p = 0; p < C::NP; ++p) xin[p] = *(const u16x8*)(Pin + p * pstride + g);
+            for (int p = 0; p < C::NP; ++p) xin[j][p] = *(const u16x8*)(Pin + p * pstride + g);
+        }
+        // one run per trip (the plane encoding is long code); the prefetched
+        // runs shift down one register slot per trip
+#pragma unroll 1
+        for (int j = 0; j < RPT; ++j) {
+            const int q = threadIdx.x + j * C::NT;
+            const int r = q / RUNS_PER_ROW, c0 = (q % RUNS_PER_ROW) * RUN;
+            const size_t g = (size_t)(rbase + r) * ldp + cbase + c0;
+            u16x8 xout[C::NP];
 #pragma unroll
             for (int k = 0; k < RUN; ++k) {
                 const int c = c0 + k;
-                // S at (row r, col c) of this pass's tile
-                double sd;
-                if (pass == 1) sd = Cs[c * C::CLD + r];                        // mirrored tile
-                else if (diag && c > r) sd = Cs[c * C::CLD + r];               // upper half of a diagonal tile
-                else sd = Cs[r * C::CLD + c];
+                // S at (row r, col c) of this pass's tile: transposed for the
+                // mirrored tile and for the upper half of a diagonal tile
+                const bool tr = mirrored || (diag && c > r);
+                const double sd = Cs[tr ? c * C::CLD + r : r * C::CLD + c];
                 E v[C::NP];
 #pragma unroll
-                for (int p = 0; p < C::NP; ++p) v[p] = xin[p][k];
+                for (int p = 0; p < C::NP; ++p) v[p] = xin[0][p][k];
                 const double x = Planes<C::MODE>::decode(v);
                 const double xn = grow ? (2.0 * x - sd) : sd;
-                if (pass == 0) {
+                if (!mirrored) {
                     const double d = sd - x;
-                    const double wgt = diag ? 1.0 : 2.0;
                     e2 += wgt * (d * d);
                     fro += wgt * (xn * xn);
                     if (diag && c == r) trp += xn;
@@ -293,6 +310,10 @@ __device__ __forceinline__ void lp_epilogue(const typename C::Elem* __restrict__
             }
 #pragma unroll
             for (int p = 0; p < C::NP; ++p) *(u16x8*)(Pout + p * pstride + g) = xout[p];
+#pragma unroll
+            for (int jj = 0; jj + 1 < RPT; ++jj)
+#pragma unroll
+                for (int p = 0; p < C::NP; ++p) xin[jj][p] = xin[jj + 1][p];
         }
     }
 }
@@ -302,17 +323,16 @@ __device__ __forceinline__ void lp_epilogue(const typename C::Elem* __restrict__
 // where the loop has just handed over to the FP64 refinement (phase 2 with
 // the iterate only in planes), it instead decodes the planes into the FP64
 // iterate X that the FP64 step launched next reads.  Otherwise it returns at
-// once.
+// once.  No workgroup waits for another: the split tiles and the steering
+// are k_sk_finish's, launched next.
 template <class C>
 __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __restrict__ Pin,
                                                    typename C::Elem* __restrict__ Pout, size_t pstride,
                                                    double* __restrict__ X, int ldp, int T, State* st,
                                                    double* __restrict__ part,
-                                                   double* __restrict__ scratch,
-                                                   unsigned* __restrict__ cnt, int step) {
+                                                   double* __restrict__ scratch, int step) {
     extern __shared__ __attribute__((aligned(16))) char lsmem[];
     __shared__ double red[C::NW];
-    __shared__ int flag;
 
     if (st->done || st->iterations != step) return;
     const int phase = st->phase;
@@ -335,7 +355,7 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __res
     const int tid = threadIdx.x;
     double* Cs = (double*)lsmem;       // the stage buffers are free after a main loop
 
-    auto run = [&](unsigned t, int ti, int tj, int k0, int k1) {
+    auto run = [&](int ti, int tj, int k0, int k1) {
         d4 acc[C::MI][C::NI];
         f4 accx[C::MI][C::NI];
 #pragma unroll
@@ -363,82 +383,44 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __res
         }
     };
 
-    // data-parallel waves over the grouped raster: the workgroups of one XCD
-    // start their tiles at K = 0 together and share row and column panels in L2
-    for (unsigned w = 0; w < waves; ++w) {
-        const unsigned t = w * G + g;
-        int ti, tj;
-        grouped_tile(t, T, 8, ti, tj);
-        run(t, ti, tj, 0, KT);
-        finish(t, ti, tj);
-    }
-
-    // stream-K remainder (the scheme of k_syrk_f64_hyb): R * KT slices over the
-    // first Gs workgroups, ranges at least KT/16 long; each segment of a split
-    // tile is an FP64 partial tile in slot 2g (first tile of the range) or
-    // 2g + 1; the tile's last segment to arrive adds them in workgroup order
+    // stream-K remainder first (the split of SkSplit): each segment of a split
+    // tile leaves its FP64 partial tile in slot 2g (the range's first tile) or
+    // 2g + 1; k_sk_finish adds them after this kernel.  Running the remainder
+    // before the data-parallel waves keeps its stores out of the waves' way.
     if (R > 0) {
-        const unsigned U = R * (unsigned)KT;
-        const unsigned minr = KT >= 16 ? (unsigned)KT / 16u : 1u;
-        const unsigned Gs = (U / minr < G) ? (U / minr > 0 ? U / minr : 1u) : G;
+        const SkSplit sk(R, (unsigned)KT, G);
         // remainder owners by hardware block index: blocks are dealt round-robin
-        // to the XCDs, so the Gs owners spread over all of them
+        // to the XCDs, so the owners spread over all of them
         const unsigned gr = blockIdx.x;
-        const unsigned u0 = gr < Gs ? (U * gr) / Gs : U;
-        const unsigned u1 = gr < Gs ? (U * (gr + 1)) / Gs : U;
-        unsigned u = u0;
+        unsigned u, u1;
+        sk.range(gr, u, u1);
         int seg_no = 0;
         while (u < u1) {
             const unsigned r = u / (unsigned)KT;
             const int k0 = (int)(u - r * (unsigned)KT);
             const unsigned kend = (unsigned)k0 + (u1 - u);
             const int k1 = kend < (unsigned)KT ? (int)kend : KT;
-            const unsigned t = Dt + r;
             int ti, tj;
-            grouped_tile(t, T, 8, ti, tj);
-            run(t, ti, tj, k0, k1);
+            grouped_tile(Dt + r, T, 8, ti, tj);
+            run(ti, tj, k0, k1);
             u += (unsigned)(k1 - k0);
-            const int slot = seg_no++;
-            if (k0 == 0 && k1 == KT) {
-                finish(t, ti, tj);
-                continue;
+            d2* mine = (d2*)(scratch + (2 * (size_t)gr + seg_no++) * (size_t)C::BT * C::BT);
+            for (int i = tid; i < C::BT * C::BT / 2; i += C::NT) {
+                const int e = 2 * i;
+                mine[i] = d2{Cs[(e / C::BT) * C::CLD + (e % C::BT)], Cs[(e / C::BT) * C::CLD + (e % C::BT) + 1]};
             }
-            const unsigned ts = r * (unsigned)KT, te = ts + (unsigned)KT;
-            const unsigned ga = ((ts + 1) * Gs - 1) / U;
-            const unsigned gb = (te * Gs - 1) / U;
-            const size_t tile_elems = (size_t)C::BT * C::BT;
-            double* mine = scratch + (2 * (size_t)gr + slot) * tile_elems;
-            for (int i = tid; i < C::BT * C::BT; i += C::NT) mine[i] = Cs[(i / C::BT) * C::CLD + (i % C::BT)];
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) flag = (int)atomicAdd(&cnt[r], 1u);
-            __syncthreads();
-            if (flag != (int)(gb - ga)) continue;    // not the last segment to arrive
-            __threadfence();
-            for (int i = tid; i < C::BT * C::BT; i += C::NT) {
-                double v = 0.0;
-                for (unsigned q = ga; q <= gb; ++q) {
-                    const unsigned qs = ((U * q) / Gs / (unsigned)KT == r) ? 0u : 1u;
-                    v += scratch[(2 * (size_t)q + qs) * tile_elems + i];
-                }
-                Cs[(i / C::BT) * C::CLD + (i % C::BT)] = v;
-            }
-            if (tid == 0) cnt[r] = 0u;
-            __syncthreads();
-            finish(t, ti, tj);
+            __syncthreads();   // the next main loop refills this LDS
         }
     }
-    if (!group_arrive_last(&st->ticket, G, &flag)) return;
-    double E = 0.0, TR = 0.0, F = 0.0;
-    for (unsigned k = tid; k < ntiles; k += C::NT) {
-        E += part[4 * k + 0];
-        TR += part[4 * k + 1];
-        F += part[4 * k + 2];
+    // data-parallel waves over the grouped raster: the workgroups of one XCD
+    // run their tiles' K slices in step and share row and column panels in L2
+    for (unsigned w = 0; w < waves; ++w) {
+        const unsigned t = w * G + g;
+        int ti, tj;
+        grouped_tile(t, T, 8, ti, tj);
+        run(ti, tj, 0, KT);
+        finish(t, ti, tj);
     }
-    E = group_sum<C::NW>(E, red);
-    TR = group_sum<C::NW>(TR, red);
-    F = group_sum<C::NW>(F, red);
-    if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
 }
 
 // The planes of the FP64 iterate, once, when the FP64 prefix hands over to the
@@ -480,7 +462,10 @@ static hipError_t launch_lp_cfg(const Layout& L, const void* Pin_, void* Pout_, 
     if (G > L.lp_groups) G = L.lp_groups;   // the workspace holds 2 G partial 128-tiles and G counters
     if (G < 1) G = 1;
     hipLaunchKernelGGL(k_syrk_lp<C>, dim3(G), dim3(C::NT), C::LDS, s, Pin, Pout, L.plane_stride, X,
-                       L.ldp, T, st, part, scratch, cnt, step);
+                       L.ldp, T, st, part, scratch, step);
+    const PlaneIO<C::MODE> io{Pin, Pout, L.plane_stride};
+    hipLaunchKernelGGL((k_sk_finish<C::BT, PlaneIO<C::MODE>, true>), dim3(sk_finish_grid(T * (T + 1) / 2, G, C::BT)),
+                       dim3(kFixThreads), 0, s, io, L.ldp, T, C::KE, st, part, scratch, (unsigned)G, step);
     return hipGetLastError();
 }
 
