@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(T* __restrict__ D, int n,
         const size_t idx = (size_t)i * ldp + j;
         if (special == 1) v = 0.0;
         else if (special == 2) v = (i == j) ? 1.0 : 0.0;
-        else if (from_planes) v = load_planes<PM>(psrc, pstride, idx);
+        else if (from_planes) v = load_planes<PM>(psrc, pstride, ldp, (size_t)i, (size_t)j);
         else v = src[idx];
         D[(size_t)i * ld + j] = (T)v;
     }

@@ -59,7 +59,10 @@ struct PlaneIO {
     const E* in;
     E* out;
     size_t pstride;
-    __device__ void load8(size_t g, double (&x)[8]) const {
+    int ldp;
+    // eight columns j..j+7 of row i (j a multiple of 8: one plane slice)
+    __device__ void load8(size_t i, size_t j, double (&x)[8]) const {
+        const size_t g = plane_off<MODE>(i, j, ldp);
         v8 p[Planes<MODE>::NP];
 #pragma unroll
         for (int q = 0; q < Planes<MODE>::NP; ++q) p[q] = *(const v8*)(in + q * pstride + g);
@@ -71,7 +74,8 @@ struct PlaneIO {
             x[k] = Planes<MODE>::decode(v);
         }
     }
-    __device__ void store8(size_t g, const double (&x)[8]) const {
+    __device__ void store8(size_t i, size_t j, const double (&x)[8]) const {
+        const size_t g = plane_off<MODE>(i, j, ldp);
         v8 p[Planes<MODE>::NP];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -89,7 +93,9 @@ struct PlaneIO {
 struct F64IO {
     const double* in;
     double* out;
-    __device__ void load8(size_t g, double (&x)[8]) const {
+    int ldp;
+    __device__ void load8(size_t i, size_t j, double (&x)[8]) const {
+        const size_t g = i * (size_t)ldp + j;
         const d4 a = *(const d4*)(in + g), b = *(const d4*)(in + g + 4);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -97,7 +103,8 @@ struct F64IO {
             x[k + 4] = b[k];
         }
     }
-    __device__ void store8(size_t g, const double (&x)[8]) const {
+    __device__ void store8(size_t i, size_t j, const double (&x)[8]) const {
+        const size_t g = i * (size_t)ldp + j;
         *(d4*)(out + g) = d4{x[0], x[1], x[2], x[3]};
         *(d4*)(out + g + 4) = d4{x[4], x[5], x[6], x[7]};
     }
@@ -199,8 +206,8 @@ __global__ __launch_bounds__(kFixThreads) void k_sk_finish(IO io, int ldp, int T
     if (tid < kFixRows * RUNS) {
         const int rr = tid / RUNS, c0 = (tid % RUNS) * 8;
         const int rl = r0 + rr;                            // row inside the tile
-        const size_t g = (size_t)(ti * BT + rl) * ldp + tj * BT + c0;
-        io.load8(g, x);
+        const size_t gi = (size_t)(ti * BT + rl), gj = (size_t)(tj * BT + c0);
+        io.load8(gi, gj, x);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int c = c0 + k;
@@ -212,17 +219,17 @@ __global__ __launch_bounds__(kFixThreads) void k_sk_finish(IO io, int ldp, int T
             fro += wgt * (xn[k] * xn[k]);
             if (diag && c == rl) trp += xn[k];
         }
-        io.store8(g, xn);
+        io.store8(gi, gj, xn);
     } else if (!diag && tid - kFixRows * RUNS < BT) {
         const int c = tid - kFixRows * RUNS;
-        const size_t g = (size_t)(tj * BT + c) * ldp + ti * BT + r0;
-        io.load8(g, x);                                    // X is bitwise symmetric
+        const size_t gi = (size_t)(tj * BT + c), gj = (size_t)(ti * BT + r0);
+        io.load8(gi, gj, x);                               // X is bitwise symmetric
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const double sd = Srow[k][c];
             xn[k] = grow ? (2.0 * x[k] - sd) : sd;
         }
-        io.store8(g, xn);
+        io.store8(gi, gj, xn);
     }
     e2 = group_sum<kFixThreads / 64>(e2, red);
     trp = group_sum<kFixThreads / 64>(trp, red);

@@ -178,21 +178,37 @@ template <> struct Planes<SP2_C_FP8> {
     }
 };
 
-// Write the planes of value x at element offset `idx` (plane p lives at
+// Plane storage is K-slice-tiled: the 64-byte slice s of every row (columns
+// s KE .. s KE + KE - 1, KE = 64 / element bytes) is contiguous over the ldp
+// rows, so the slice of a 128-row panel that one main-loop stage loads is a
+// single 8 KB block (whole 128-byte lines, 1 KB per wave instruction) rather
+// than 128 half lines one row apart:
+//   offset(i, j) = ((j / KE) ldp + i) KE + j mod KE.
+template <int MODE>
+__device__ inline size_t plane_off(size_t i, size_t j, int ldp) {
+    constexpr size_t KE = 64 / sizeof(typename Planes<MODE>::Elem);
+    return ((j / KE) * (size_t)ldp + i) * KE + (j % KE);
+}
+
+// Write the planes of value x at element (i, j) (plane p lives at
 // base + p * pstride).
 template <int MODE>
-__device__ inline void store_planes(typename Planes<MODE>::Elem* base, size_t pstride, size_t idx, double x) {
+__device__ inline void store_planes(typename Planes<MODE>::Elem* base, size_t pstride, int ldp, size_t i,
+                                    size_t j, double x) {
     typename Planes<MODE>::Elem v[Planes<MODE>::NP];
     Planes<MODE>::encode(x, v);
+    const size_t o = plane_off<MODE>(i, j, ldp);
 #pragma unroll
-    for (int p = 0; p < Planes<MODE>::NP; ++p) base[p * pstride + idx] = v[p];
+    for (int p = 0; p < Planes<MODE>::NP; ++p) base[p * pstride + o] = v[p];
 }
 
 template <int MODE>
-__device__ inline double load_planes(const typename Planes<MODE>::Elem* base, size_t pstride, size_t idx) {
+__device__ inline double load_planes(const typename Planes<MODE>::Elem* base, size_t pstride, int ldp, size_t i,
+                                     size_t j) {
     typename Planes<MODE>::Elem v[Planes<MODE>::NP];
+    const size_t o = plane_off<MODE>(i, j, ldp);
 #pragma unroll
-    for (int p = 0; p < Planes<MODE>::NP; ++p) v[p] = base[p * pstride + idx];
+    for (int p = 0; p < Planes<MODE>::NP; ++p) v[p] = base[p * pstride + o];
     return Planes<MODE>::decode(v);
 }
 

@@ -269,7 +269,7 @@ static hipError_t launch_hyb(const Layout& L, const double* X, double* Y, State*
     if (G < 1) G = 1;
     hipLaunchKernelGGL(k_syrk_f64_hyb<C>, dim3(G), dim3(C::NT), lds, s, X, Y, L.ldp, T, st, part, scratch, step);
     hipLaunchKernelGGL((k_sk_finish<C::BT, F64IO, false>), dim3(sk_finish_grid(T * (T + 1) / 2, G, C::BT)),
-                       dim3(kFixThreads), 0, s, F64IO{X, Y}, L.ldp, T, kBK, st, part, scratch, (unsigned)G, step);
+                       dim3(kFixThreads), 0, s, F64IO{X, Y, L.ldp}, L.ldp, T, kBK, st, part, scratch, (unsigned)G, step);
     return hipGetLastError();
 }
 

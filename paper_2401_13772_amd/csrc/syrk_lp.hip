@@ -25,10 +25,12 @@
 //     64 x 32 (4 x 2 blocks of 16 x 16; FP64 + FP32 accumulators = 24 VGPRs
 //     per block);
 //   * operand panels go straight from global memory to LDS with the 16-byte
-//     LDS-DMA load (global_load_lds_dwordx4): no staging registers.  Each
-//     wave instruction fills 1 KiB = 16 rows x 64 B; a row's four 16-byte
-//     chunks are stored XOR-swizzled by (row >> 1) & 3 so that the eight lanes
-//     a ds_read_b128 serves per cycle hit distinct banks;
+//     LDS-DMA load (global_load_lds_dwordx4): no staging registers.  The
+//     planes are stored K-slice-tiled (plane_off), so a panel's slice is one
+//     contiguous 8 KB block and each wave instruction reads 1 KiB = 16 rows x
+//     64 B of whole 128-byte lines; a row's four 16-byte chunks are stored
+//     XOR-swizzled by (row >> 1) & 3 so that the eight lanes a ds_read_b128
+//     serves per cycle hit distinct banks;
 //   * up to four K slices of 32 elements in LDS (three loading while one is
 //     multiplied), one barrier per slice;
 //   * the schedule of the 128-tile FP64 step: grouped raster, K-synchronous
@@ -69,7 +71,7 @@ struct LpCfg {
     static constexpr int BLOCKS = PANEL_BYTES / 1024;           // 1 KiB LDS-DMA blocks per panel plane
     static constexpr int BPW = BLOCKS / NW;                     // ... per wave
     static_assert(BLOCKS % NW == 0, "panel must split evenly over the waves");
-    static_assert(LDS <= 160 * 1024, "LDS budget of one CU");
+    static_assert(LDS + 256 <= 160 * 1024, "LDS budget of one CU (with the kernel's static LDS)");
 };
 
 // The product of one 16-byte fragment pair: 8 elements of each of the lane's
@@ -108,7 +110,9 @@ __device__ __forceinline__ void lp_issue(const typename C::Elem* __restrict__ P,
                 const int blk = w * C::BPW + j;
                 const int row = blk * 16 + (lane >> 2);
                 const int c = (lane & 3) ^ swz(row);
-                const typename C::Elem* src = P + p * pstride + (size_t)(prow0 + row) * ldp + k0 +
+                // the K-slice-tiled plane: this slice of the panel's 128 rows is
+                // one 8 KB block, 16 rows (1 KB) per wave instruction
+                const typename C::Elem* src = P + p * pstride + ((size_t)(k0 / C::KE) * ldp + prow0 + row) * C::KE +
                                               c * (16 / (int)sizeof(typename C::Elem));
                 char* dst = stage + (p * 2 + q) * C::PANEL_BYTES + blk * 1024;
                 __builtin_amdgcn_global_load_lds((const void*)src,
@@ -162,6 +166,15 @@ __device__ __forceinline__ void lp_mainloop(const typename C::Elem* __restrict__
         boff[ni] = row * 64 + (((lane >> 4) ^ swz(row)) << 4);
     }
     const f4 zero = {0.f, 0.f, 0.f, 0.f};
+    // the leading term of the previous slice, promoted into FP64 one slice
+    // late: its conversions and FP64 adds then never wait for an MFMA in
+    // flight and overlap this slice's MFMAs (zero before the first slice:
+    // adding +0.0 to the +0.0 accumulators changes no bit)
+    f4 tl[C::MI][C::NI];
+#pragma unroll
+    for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < C::NI; ++ni) tl[mi][ni] = zero;
     int slot = 0;
     for (int kt = kt0; kt < kt1; ++kt) {
         const int ahead = (kt1 - 1 - kt) < (C::NS - 2) ? (kt1 - 1 - kt) : (C::NS - 2);
@@ -187,6 +200,15 @@ __device__ __forceinline__ void lp_mainloop(const typename C::Elem* __restrict__
 #pragma unroll
             for (int ni = 0; ni < C::NI; ++ni) bf[p][ni] = *(const uint4*)(pb + boff[ni]);
         }
+        // leading term: one slice per MFMA; the previous slice's goes to FP64
+#pragma unroll
+        for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < C::NI; ++ni) {
+                const f4 t = tl[mi][ni];
+                acc[mi][ni] += d4{(double)t[0], (double)t[1], (double)t[2], (double)t[3]};
+                tl[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[0][ni], zero);
+            }
         // correction terms, smallest first, into the FP32 accumulator
         if constexpr (C::NP == 3) {
 #pragma unroll
@@ -205,15 +227,14 @@ __device__ __forceinline__ void lp_mainloop(const typename C::Elem* __restrict__
                 accx[mi][ni] = mfma16<C::MODE>(af[1][mi], bf[0][ni], accx[mi][ni]);
                 accx[mi][ni] = mfma16<C::MODE>(af[0][mi], bf[1][ni], accx[mi][ni]);
             }
-        // leading term: one slice per MFMA, promoted into FP64
-#pragma unroll
-        for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < C::NI; ++ni) {
-                const f4 t = mfma16<C::MODE>(af[0][mi], bf[0][ni], zero);
-                acc[mi][ni] += d4{(double)t[0], (double)t[1], (double)t[2], (double)t[3]};
-            }
     }
+#pragma unroll
+    for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < C::NI; ++ni) {
+            const f4 t = tl[mi][ni];
+            acc[mi][ni] += d4{(double)t[0], (double)t[1], (double)t[2], (double)t[3]};
+        }
     __syncthreads();   // every wave is done with the stages before the LDS is reused
 }
 
@@ -273,7 +294,7 @@ __device__ __forceinline__ void lp_epilogue(const typename C::Elem* __restrict__
         for (int j = 0; j < RPT; ++j) {
             const int q = threadIdx.x + j * C::NT;
             const int r = q / RUNS_PER_ROW, c0 = (q % RUNS_PER_ROW) * RUN;
-            const size_t g = (size_t)(rbase + r) * ldp + cbase + c0;
+            const size_t g = plane_off<C::MODE>((size_t)(rbase + r), (size_t)(cbase + c0), ldp);
 #pragma unroll
             for (int p = 0; p < C::NP; ++p) xin[j][p] = *(const u16x8*)(Pin + p * pstride + g);
         }
@@ -283,7 +304,7 @@ __device__ __forceinline__ void lp_epilogue(const typename C::Elem* __restrict__
         for (int j = 0; j < RPT; ++j) {
             const int q = threadIdx.x + j * C::NT;
             const int r = q / RUNS_PER_ROW, c0 = (q % RUNS_PER_ROW) * RUN;
-            const size_t g = (size_t)(rbase + r) * ldp + cbase + c0;
+            const size_t g = plane_off<C::MODE>((size_t)(rbase + r), (size_t)(cbase + c0), ldp);
             u16x8 xout[C::NP];
 #pragma unroll
             for (int k = 0; k < RUN; ++k) {
@@ -340,7 +361,7 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __res
         if (!st->stale) return;
         const size_t count = (size_t)ldp * ldp;
         for (size_t i = (size_t)blockIdx.x * C::NT + threadIdx.x; i < count; i += (size_t)gridDim.x * C::NT)
-            X[i] = load_planes<C::MODE>(Pin, pstride, i);
+            X[i] = load_planes<C::MODE>(Pin, pstride, ldp, i / (size_t)ldp, i % (size_t)ldp);
         return;
     }
     if (phase != 1) return;
@@ -428,12 +449,12 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __res
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_f64_to_planes(const double* __restrict__ X,
                                                             typename Planes<MODE>::Elem* __restrict__ Pout,
-                                                            size_t pstride,
+                                                            size_t pstride, int ldp,
                                                             size_t count, const State* st, int step) {
     if (st->done || st->iterations != step || st->phase != 1 || st->lp_steps != 0) return;
     for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < count;
          i += (size_t)gridDim.x * kThreads)
-        store_planes<MODE>(Pout, pstride, i, X[i]);
+        store_planes<MODE>(Pout, pstride, ldp, i / (size_t)ldp, i % (size_t)ldp, X[i]);
 }
 
 template <class C>
@@ -463,7 +484,7 @@ static hipError_t launch_lp_cfg(const Layout& L, const void* Pin_, void* Pout_, 
     if (G < 1) G = 1;
     hipLaunchKernelGGL(k_syrk_lp<C>, dim3(G), dim3(C::NT), C::LDS, s, Pin, Pout, L.plane_stride, X,
                        L.ldp, T, st, part, scratch, step);
-    const PlaneIO<C::MODE> io{Pin, Pout, L.plane_stride};
+    const PlaneIO<C::MODE> io{Pin, Pout, L.plane_stride, L.ldp};
     hipLaunchKernelGGL((k_sk_finish<C::BT, PlaneIO<C::MODE>, true>), dim3(sk_finish_grid(T * (T + 1) / 2, G, C::BT)),
                        dim3(kFixThreads), 0, s, io, L.ldp, T, C::KE, st, part, scratch, (unsigned)G, step);
     return hipGetLastError();
@@ -493,7 +514,7 @@ template <int MODE>
 static void f64_to_planes_t(const Layout& L, const double* X, void* Pout, const State* st, int step, hipStream_t s) {
     const size_t count = (size_t)L.ldp * L.ldp;
     hipLaunchKernelGGL(k_f64_to_planes<MODE>, dim3(2048), dim3(kThreads), 0, s, X,
-                       (typename Planes<MODE>::Elem*)Pout, L.plane_stride, count, st, step);
+                       (typename Planes<MODE>::Elem*)Pout, L.plane_stride, L.ldp, count, st, step);
 }
 
 hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, void* Pout,
