@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsp2.so")
 
-SOURCES = ["bounds_init.hip", "syrk_f64.hip", "syrk_lp.hip", "sp2_api.hip", "sp2_noalloc.hip", "sp2_batch.hip", "sp2_learned.hip", "sp2_cheb.hip", "sp2_graph.hip", "sp2_sparse.hip"]
+SOURCES = ["bounds_init.hip", "syrk_f64.hip", "syrk_lp.hip", "step_end.hip", "sp2_api.hip", "sp2_noalloc.hip", "sp2_batch.hip", "sp2_learned.hip", "sp2_cheb.hip", "sp2_graph.hip", "sp2_sparse.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

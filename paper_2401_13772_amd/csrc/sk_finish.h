@@ -1,22 +1,24 @@
-// sk_finish.h -- the second kernel of a 128-tile SP2 step (FP64 or split
-// operands): it completes the tiles that the step's stream-K remainder split
-// over several workgroups and then takes the step's steering decision.
+// sk_finish.h -- the kernels that end a 128-tile SP2 step (FP64 or split
+// operands): k_step_finish completes the tiles that the step's stream-K
+// remainder split over several workgroups, k_step_steer takes the step's
+// steering decision.
 //
 // The step kernel (k_syrk_f64_hyb, k_syrk_lp) leaves every split tile as FP64
 // partial tiles in its scratch and every whole tile's sums (e^2, trace,
-// ||X'||^2) in `part`; it uses no cross-workgroup fence or counter.  A kernel
-// boundary orders its writes before this kernel's reads on every XCD, which an
-// in-kernel hand-over can only get from agent-scope release/acquire fences
-// (an L2 write-back and invalidate on each XCD, measured at tens of
-// microseconds per step on MI355X).
+// ||X'||^2) in `part`; it uses no cross-workgroup fence or counter.  Kernel
+// boundaries order each kernel's writes before the next one's reads on every
+// XCD, which an in-kernel hand-over can only get from agent-scope
+// release/acquire fences (an L2 write-back and invalidate on each XCD,
+// measured at about 20 microseconds per fence round on MI355X).
 //
-// Grid: R * (BT / kFixRows) workgroups for R split tiles (one 8-row block of a
-// tile each), or one workgroup when R = 0.  Each adds the tile's partials for its
-// rows in workgroup order (the same order and operands as a single workgroup
-// summing the whole tile), applies the SP2 update to its rows and to the
-// mirrored columns, and stores its sums in `part` after the whole tiles'.
-// The last workgroup to arrive (one cheap fence: this kernel's own writes are
-// all that is dirty) adds `part` in index order and steers.
+// k_step_finish: R * (BT / kFixRows) workgroups for R split tiles (one 8-row
+// block of a tile each).  Each adds the tile's partials for its rows in
+// workgroup order (the same order and operands as a single workgroup summing
+// the whole tile), applies the SP2 update to its rows and to the mirrored
+// columns, and stores its sums in `part` after the whole tiles'.
+// k_step_steer: one workgroup adds `part` in index order and steers.
+// Both serve whichever step ran (split-operand in phase 1, FP64 otherwise);
+// a 64-tile FP64 step steers itself and they return at once.
 #pragma once
 
 #include "syrk_f64_core.h"
@@ -60,17 +62,23 @@ struct PlaneIO {
     E* out;
     size_t pstride;
     int ldp;
-    // eight columns j..j+7 of row i (j a multiple of 8: one plane slice)
-    __device__ void load8(size_t i, size_t j, double (&x)[8]) const {
-        const size_t g = plane_off<MODE>(i, j, ldp);
+    struct Raw {
         v8 p[Planes<MODE>::NP];
+    };
+    // eight columns j..j+7 of row i (j a multiple of 8: one plane slice)
+    __device__ Raw fetch(size_t i, size_t j) const {
+        const size_t g = plane_off<MODE>(i, j, ldp);
+        Raw r;
 #pragma unroll
-        for (int q = 0; q < Planes<MODE>::NP; ++q) p[q] = *(const v8*)(in + q * pstride + g);
+        for (int q = 0; q < Planes<MODE>::NP; ++q) r.p[q] = *(const v8*)(in + q * pstride + g);
+        return r;
+    }
+    __device__ static void decode(const Raw& r, double (&x)[8]) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             E v[Planes<MODE>::NP];
 #pragma unroll
-            for (int q = 0; q < Planes<MODE>::NP; ++q) v[q] = p[q][k];
+            for (int q = 0; q < Planes<MODE>::NP; ++q) v[q] = r.p[q][k];
             x[k] = Planes<MODE>::decode(v);
         }
     }
@@ -94,13 +102,18 @@ struct F64IO {
     const double* in;
     double* out;
     int ldp;
-    __device__ void load8(size_t i, size_t j, double (&x)[8]) const {
+    struct Raw {
+        d4 a, b;
+    };
+    __device__ Raw fetch(size_t i, size_t j) const {
         const size_t g = i * (size_t)ldp + j;
-        const d4 a = *(const d4*)(in + g), b = *(const d4*)(in + g + 4);
+        return Raw{*(const d4*)(in + g), *(const d4*)(in + g + 4)};
+    }
+    __device__ static void decode(const Raw& r, double (&x)[8]) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            x[k] = a[k];
-            x[k + 4] = b[k];
+            x[k] = r.a[k];
+            x[k + 4] = r.b[k];
         }
     }
     __device__ void store8(size_t i, size_t j, const double (&x)[8]) const {
@@ -124,12 +137,12 @@ __device__ inline void sk_steer(State* st, const double* part, unsigned entries,
     if (threadIdx.x == 0) sp2_steer_thread0(st, E, TR, F, grow);
 }
 
-// LP: the kernel serves the split-operand phase (phase 1), else the FP64 one.
-template <int BT, class IO, bool LP>
-__global__ __launch_bounds__(kFixThreads) void k_sk_finish(IO io, int ldp, int T, int KE, State* st,
-                                                           double* __restrict__ part,
-                                                           const double* __restrict__ scratch,
-                                                           unsigned G, int step) {
+// One kFixRows-row block (blk) of split tile r of a step over T x T tiles of
+// BT, whose stream-K remainder ran on G workgroups with K slices of KE
+// elements.
+template <int BT, class IO>
+__device__ void sk_fix_block(const IO& io, int ldp, int T, int KE, unsigned G, unsigned blk, int grow,
+                             double* __restrict__ part, const double* __restrict__ scratch) {
     constexpr int FB = BT / kFixRows;          // row blocks per tile
     constexpr int RUNS = BT / 8;               // 8-element runs per tile row
     static_assert(kFixRows == 8 && kFixRows * RUNS <= kFixThreads && BT <= kFixThreads,
@@ -139,21 +152,13 @@ __global__ __launch_bounds__(kFixThreads) void k_sk_finish(IO io, int ldp, int T
     __shared__ double Srow[kFixRows][BT];      // S rows r0..r0+7
     __shared__ double Scol[BT][kFixRows + 1];  // S columns r0..r0+7 (diagonal tiles)
     __shared__ double red[kFixThreads / 64];
-    __shared__ int flag;
 
-    if (st->done || st->iterations != step) return;
-    if (LP != (st->phase == 1)) return;
-    const int grow = st->grow;
     const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
     const unsigned Dt = (ntiles / G) * G;
     const unsigned R = ntiles - Dt;
-    if (R == 0) {                              // one workgroup: the step kernel's sums are visible
-        sk_steer(st, part, Dt, grow, red);
-        return;
-    }
     const int tid = threadIdx.x;
-    const unsigned r = blockIdx.x / FB;
-    const int b = (int)(blockIdx.x % FB), r0 = b * kFixRows;
+    const unsigned r = blk / FB;
+    const int b = (int)(blk % FB), r0 = b * kFixRows;
     const unsigned t = Dt + r;
     int ti, tj;
     grouped_tile(t, T, 8, ti, tj);
@@ -163,25 +168,51 @@ __global__ __launch_bounds__(kFixThreads) void k_sk_finish(IO io, int ldp, int T
     sk.owners(r, ga, gb);
     const size_t tile_elems = (size_t)BT * BT;
 
+    // this thread's run of X (rows, or the mirrored columns), fetched first so
+    // that its latency overlaps the partial sums
+    const bool rows = tid < kFixRows * RUNS;
+    const bool mirror = !diag && !rows && tid - kFixRows * RUNS < BT;
+    size_t gi = 0, gj = 0;
+    if (rows) {
+        gi = (size_t)(ti * BT + r0 + tid / RUNS);
+        gj = (size_t)(tj * BT + (tid % RUNS) * 8);
+    } else if (mirror) {
+        gi = (size_t)(tj * BT + tid - kFixRows * RUNS);
+        gj = (size_t)(ti * BT + r0);
+    }
+    typename IO::Raw xraw{};
+    if (rows || mirror) xraw = io.fetch(gi, gj);
+
     // S rows (and for a diagonal tile S columns) of this block: the partials
-    // added in workgroup order, two element pairs per thread
+    // added in workgroup order, two element pairs per thread; QB partials'
+    // loads in flight at a time
     {
+        constexpr int QB = 8;
         d2 vr[2], vc[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) vr[j] = vc[j] = d2{0.0, 0.0};
-        for (unsigned q = ga; q <= gb; ++q) {
-            const double* P = scratch + (2 * (size_t)q + sk.slot(q, r)) * tile_elems;
-            d2 a[2], c[2] = {d2{0.0, 0.0}, d2{0.0, 0.0}};
+        for (unsigned q0 = ga; q0 <= gb; q0 += QB) {
+            d2 a[QB][2], c[QB][2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int p = tid + j * kFixThreads;
-                a[j] = *(const d2*)(P + (size_t)(r0 + p / (BT / 2)) * BT + 2 * (p % (BT / 2)));
-                if (diag) c[j] = *(const d2*)(P + (size_t)(p / 4) * BT + r0 + 2 * (p % 4));
+            for (int u = 0; u < QB; ++u) {
+                const unsigned q = q0 + u;
+                if (q > gb) break;
+                const double* P = scratch + (2 * (size_t)q + sk.slot(q, r)) * tile_elems;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int p = tid + j * kFixThreads;
+                    a[u][j] = *(const d2*)(P + (size_t)(r0 + p / (BT / 2)) * BT + 2 * (p % (BT / 2)));
+                    if (diag) c[u][j] = *(const d2*)(P + (size_t)(p / 4) * BT + r0 + 2 * (p % 4));
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                vr[j] += a[j];
-                if (diag) vc[j] += c[j];
+            for (int u = 0; u < QB; ++u) {
+                if (q0 + u > gb) break;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    vr[j] += a[u][j];
+                    if (diag) vc[j] += c[u][j];
+                }
             }
         }
 #pragma unroll
@@ -203,11 +234,10 @@ __global__ __launch_bounds__(kFixThreads) void k_sk_finish(IO io, int ldp, int T
     double e2 = 0.0, trp = 0.0, fro = 0.0;
     const double wgt = diag ? 1.0 : 2.0;
     double x[8], xn[8];
-    if (tid < kFixRows * RUNS) {
+    if (rows) {
         const int rr = tid / RUNS, c0 = (tid % RUNS) * 8;
         const int rl = r0 + rr;                            // row inside the tile
-        const size_t gi = (size_t)(ti * BT + rl), gj = (size_t)(tj * BT + c0);
-        io.load8(gi, gj, x);
+        IO::decode(xraw, x);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int c = c0 + k;
@@ -220,10 +250,9 @@ __global__ __launch_bounds__(kFixThreads) void k_sk_finish(IO io, int ldp, int T
             if (diag && c == rl) trp += xn[k];
         }
         io.store8(gi, gj, xn);
-    } else if (!diag && tid - kFixRows * RUNS < BT) {
+    } else if (mirror) {
         const int c = tid - kFixRows * RUNS;
-        const size_t gi = (size_t)(tj * BT + c), gj = (size_t)(ti * BT + r0);
-        io.load8(gi, gj, x);                               // X is bitwise symmetric
+        IO::decode(xraw, x);                               // X is bitwise symmetric
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const double sd = Srow[k][c];
@@ -240,14 +269,30 @@ __global__ __launch_bounds__(kFixThreads) void k_sk_finish(IO io, int ldp, int T
         part[4 * k + 1] = trp;
         part[4 * k + 2] = fro;
     }
-    if (!group_arrive_last(&st->ticket, gridDim.x, &flag)) return;
-    sk_steer(st, part, Dt + R * FB, grow, red);
+    (void)R;
 }
 
-// grid of k_sk_finish for `tiles` tiles after a step kernel of G workgroups
-inline unsigned sk_finish_grid(int tiles, int G, int bt) {
-    const unsigned R = (unsigned)(tiles % G);
-    return R ? R * (unsigned)(bt / kFixRows) : 1u;
+// The two 128-tile step shapes a solve may run: split-operand (T_lp tiles a
+// side, G_lp workgroups, K slices of KE_lp) and FP64 (T_f64, G_f64, kBK;
+// G_f64 = 0 when the FP64 step is the self-steering 64-tile kernel).
+struct StepShape {
+    int ldp;
+    int T_lp, KE_lp, G_lp;
+    int T_f64, G_f64;
+};
+
+// Blocks of the split tiles of a step over T x T tiles on G workgroups.
+__host__ __device__ inline unsigned sk_fix_blocks(int T, int G) {
+    if (G <= 0) return 0;
+    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
+    return (ntiles % (unsigned)G) * (unsigned)(kLpTile / kFixRows);
+}
+
+// Entries of `part` the step filled: whole tiles, then the split tiles' blocks.
+__device__ inline unsigned sk_entries(int T, int G) {
+    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
+    const unsigned R = ntiles % (unsigned)G;
+    return ntiles - R + R * (unsigned)(kLpTile / kFixRows);
 }
 
 }  // namespace sp2

@@ -82,7 +82,7 @@ constexpr int kMaxDevices = 16;
 
 // Optional per-step kernel timing (sp2_profile_enable): an event pair around
 // every SYRK launch on the caller's stream.
-constexpr int kLaunchesPerStep = 2;  // FP64 step kernel, split-operand step kernel
+constexpr int kLaunchesPerStep = 3;  // FP64 step kernel, split-operand step kernel, step end
 struct Profile {
     bool on = false;
     bool made = false;
@@ -266,12 +266,15 @@ int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, i
                 // split kernel decodes the planes into the FP64 iterate first.
                 if (issued == m0) SP2_HIP(launch_f64_to_planes(L, compute, xc, pc, st, issued, s));
                 if (timed) SP2_HIP(hipEventRecord(ev[2], s));
-                SP2_HIP(launch_syrk_lp(L, compute, pc, pn, xc, st, part, scratch, cnt, issued, s));
+                SP2_HIP(launch_syrk_lp(L, compute, pc, pn, xc, st, part, scratch, issued, s));
                 if (timed) SP2_HIP(hipEventRecord(ev[3], s));
             }
             if (timed) SP2_HIP(hipEventRecord(ev[0], s));
             SP2_HIP(launch_syrk_f64(L, xc, xn, st, part, scratch, cnt, issued, s));
             if (timed) SP2_HIP(hipEventRecord(ev[1], s));
+            // split tiles and steering of whichever 128-tile step ran
+            SP2_HIP(launch_step_end(L, compute, pc, pn, xc, xn, st, part, scratch, issued, s));
+            if (timed) SP2_HIP(hipEventRecord(ev[4], s));
         }
         if (no_alloc) continue;
         lease.pending = s;
@@ -302,10 +305,13 @@ int density_impl(const void* H, void* D, int n, int ld, int n_occ, double tol, i
         prof->last_steps[0] = prof->last_steps[1] = 0;
         for (int i = 0; i < h.iterations && i < issued; ++i) {
             const int lp = (int)((h.lp_mask[i >> 6] >> (i & 63)) & 1ull);
-            float ms = 0.f;
-            hipEvent_t* ev = &prof->ev[2 * kLaunchesPerStep * i + 2 * lp];
-            SP2_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-            prof->last_ms[lp] += ms;
+            // the step kernel that ran plus the step end (the other step
+            // kernel returned at once and is not counted)
+            float ms = 0.f, ms_end = 0.f;
+            hipEvent_t* ev = &prof->ev[2 * kLaunchesPerStep * i];
+            SP2_HIP(hipEventElapsedTime(&ms, ev[2 * lp], ev[2 * lp + 1]));
+            SP2_HIP(hipEventElapsedTime(&ms_end, ev[1], ev[4]));
+            prof->last_ms[lp] += ms + ms_end;
             prof->last_steps[lp] += 1;
         }
     }

@@ -82,7 +82,7 @@ struct Layout {
 };
 
 constexpr int kLpTile = 128;  // tile edge of the split-operand kernels
-constexpr int kFixRows = 8;   // S rows per workgroup of a step's finishing kernel (k_sk_finish)
+constexpr int kFixRows = 8;   // S rows per workgroup of a step's finishing kernel (k_step_finish)
 
 inline int planes_of(sp2_compute c) {
     return c == SP2_C_F16X2 ? 2 : c == SP2_C_BF16X3 ? 3 : c == SP2_C_BF16X2 ? 2 : c == SP2_C_FP8 ? 2 : 0;
@@ -241,8 +241,15 @@ hipError_t launch_init(const void* H, sp2_dtype dt, int n, int ld, const Layout&
 hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* st, double* part,
                            double* scratch, unsigned* cnt, int step, hipStream_t s);
 hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const void* Pin, void* Pout,
-                          double* X, State* st, double* part, double* scratch, unsigned* cnt,
-                          int step, hipStream_t s);
+                          double* X, State* st, double* part, double* scratch, int step, hipStream_t s);
+// Workgroups of the step kernels (0 for the self-steering 64-tile FP64 step).
+hipError_t lp_step_groups(const Layout& L, sp2_compute mode, int* G);
+hipError_t f64_step_groups(const Layout& L, int* G);
+// End of step `step`, after the step kernels: the split tiles of whichever
+// 128-tile step ran (FP64 X -> Y, or planes Pin -> Pout), then the steering.
+hipError_t launch_step_end(const Layout& L, sp2_compute mode, const void* Pin, void* Pout, const double* X,
+                           double* Y, State* st, double* part, const double* scratch, int step,
+                           hipStream_t s);
 hipError_t launch_f64_to_planes(const Layout& L, sp2_compute mode, const double* X, void* Pout,
                                 const State* st, int step, hipStream_t s);
 hipError_t launch_finalize(void* D, sp2_dtype dt, int n, int ld, const Layout& L, sp2_compute mode,

@@ -143,10 +143,10 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64(const double* __restrict__ X
 // contiguous ranges of K slices (a range is shorter than a tile, so it touches
 // at most two tiles).  Each segment of a split tile is stored as an FP64
 // partial in slot 2g (the workgroup's first tile) or 2g + 1 (its second).
-// The step's second kernel, k_sk_finish, adds a split tile's partials in
-// workgroup order (the sum does not depend on which segment finished last),
-// runs the split tiles' epilogue and takes the steering decision: this kernel
-// needs no fence or counter between its workgroups.  The remainder runs
+// The kernels launched after it (k_step_finish, k_step_steer) add a split
+// tile's partials in workgroup order (the sum does not depend on which segment
+// finished last), run the split tiles' epilogue and take the steering
+// decision: this kernel needs no fence or counter between its workgroups.  The remainder runs
 // before the waves, so its partial stores do not trail the waves.
 constexpr int kGroupM = 8;
 
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64_hyb(const double* __restrict
 
     // stream-K remainder (the split of SkSplit): each segment of a split tile
     // leaves its FP64 partial tile, row-major, in slot 2g (the range's first
-    // tile) or 2g + 1; k_sk_finish adds them after this kernel.  R < G <= 1024
+    // tile) or 2g + 1; k_step_finish adds them after this kernel.  R < G <= 1024
     // and KT <= 4096 keep every product below 2^32 (32-bit range arithmetic).
     if (R > 0) {
         const SkSplit sk(R, (unsigned)KT, G);
@@ -244,8 +244,9 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64_hyb(const double* __restrict
 
 using CfgHyb = SyrkCfg<128, 2, 2>;   // 256 threads, 64 x 64 per wave, LDS-DMA operands
 
-static hipError_t launch_hyb(const Layout& L, const double* X, double* Y, State* st, double* part,
-                             double* scratch, unsigned* cnt, int step, hipStream_t s) {
+// Workgroups of the 128-tile step: as many as are co-resident, at most
+// L.max_groups (the workspace holds 2 G partial tiles).
+static hipError_t hyb_groups(const Layout& L, int* G) {
     using C = CfgHyb;
     constexpr size_t lds = DmaLayout<C>::LDS > LdsEpi<C>::LDS ? DmaLayout<C>::LDS : LdsEpi<C>::LDS;
     static int per_cu = -1;
@@ -263,13 +264,21 @@ static hipError_t launch_hyb(const Layout& L, const double* X, double* Y, State*
         if (e != hipSuccess) return e;
         per_cu = nb < 1 ? 1 : nb;
     }
+    int g = per_cu * cus;
+    if (g > L.max_groups) g = L.max_groups;
+    *G = g < 1 ? 1 : g;
+    return hipSuccess;
+}
+
+static hipError_t launch_hyb(const Layout& L, const double* X, double* Y, State* st, double* part,
+                             double* scratch, int step, hipStream_t s) {
+    using C = CfgHyb;
+    constexpr size_t lds = DmaLayout<C>::LDS > LdsEpi<C>::LDS ? DmaLayout<C>::LDS : LdsEpi<C>::LDS;
+    int G = 0;
+    hipError_t e = hyb_groups(L, &G);
+    if (e != hipSuccess) return e;
     const int T = L.ldp / C::BT;
-    int G = per_cu * cus;
-    if (G > L.max_groups) G = L.max_groups;   // the workspace holds 2 G partial tiles and G counters
-    if (G < 1) G = 1;
     hipLaunchKernelGGL(k_syrk_f64_hyb<C>, dim3(G), dim3(C::NT), lds, s, X, Y, L.ldp, T, st, part, scratch, step);
-    hipLaunchKernelGGL((k_sk_finish<C::BT, F64IO, false>), dim3(sk_finish_grid(T * (T + 1) / 2, G, C::BT)),
-                       dim3(kFixThreads), 0, s, F64IO{X, Y, L.ldp}, L.ldp, T, kBK, st, part, scratch, (unsigned)G, step);
     return hipGetLastError();
 }
 
@@ -305,7 +314,15 @@ static hipError_t launch_cfg(const Layout& L, const double* X, double* Y, State*
 hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* st, double* part,
                            double* scratch, unsigned* cnt, int step, hipStream_t s) {
     if (L.bt == CfgSmall::BT) return launch_cfg<CfgSmall>(L, X, Y, st, part, scratch, cnt, step, s);
-    return launch_hyb(L, X, Y, st, part, scratch, cnt, step, s);
+    return launch_hyb(L, X, Y, st, part, scratch, step, s);
+}
+
+hipError_t f64_step_groups(const Layout& L, int* G) {
+    if (L.bt == CfgSmall::BT) {   // the 64-tile kernel steers itself
+        *G = 0;
+        return hipSuccess;
+    }
+    return hyb_groups(L, G);
 }
 
 }  // namespace sp2

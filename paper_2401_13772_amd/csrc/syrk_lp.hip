@@ -17,8 +17,8 @@
 // FP64 step (Section "SP2 solver": X' = X^2 or 2X - X^2 by the trace),
 // evaluated in FP64 from the decoded X and S; it writes the planes of X'
 // (they are the iterate during this phase: no FP64 copy is stored) and the
-// per-tile e^2, trace and ||X'||^2.  The step's second kernel, k_sk_finish,
-// completes the split tiles and steers (sp2_steer_thread0).
+// per-tile e^2, trace and ||X'||^2.  The kernels launched after it complete
+// the split tiles (k_step_finish) and steer (k_step_steer, sp2_steer_thread0).
 //
 // Design for CDNA4:
 //   * 128 x 128 tiles of the lower block triangle, 8 wave64s each owning
@@ -35,7 +35,7 @@
 //     multiplied), one barrier per slice;
 //   * the schedule of the 128-tile FP64 step: grouped raster, K-synchronous
 //     data-parallel waves (the workgroups of one XCD share panels in L2) and
-//     a stream-K remainder whose FP64 partial tiles k_sk_finish adds in a
+//     a stream-K remainder whose FP64 partial tiles k_step_finish adds in a
 //     fixed order.
 #include "sk_finish.h"
 
@@ -345,7 +345,7 @@ __device__ __forceinline__ void lp_epilogue(const typename C::Elem* __restrict__
 // the iterate only in planes), it instead decodes the planes into the FP64
 // iterate X that the FP64 step launched next reads.  Otherwise it returns at
 // once.  No workgroup waits for another: the split tiles and the steering
-// are k_sk_finish's, launched next.
+// are k_step_finish's and k_step_steer's, launched after it.
 template <class C>
 __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __restrict__ Pin,
                                                    typename C::Elem* __restrict__ Pout, size_t pstride,
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __res
 
     // stream-K remainder first (the split of SkSplit): each segment of a split
     // tile leaves its FP64 partial tile in slot 2g (the range's first tile) or
-    // 2g + 1; k_sk_finish adds them after this kernel.  Running the remainder
+    // 2g + 1; k_step_finish adds them after this kernel.  Running the remainder
     // before the data-parallel waves keeps its stores out of the waves' way.
     if (R > 0) {
         const SkSplit sk(R, (unsigned)KT, G);
@@ -457,12 +457,10 @@ __global__ __launch_bounds__(kThreads) void k_f64_to_planes(const double* __rest
         store_planes<MODE>(Pout, pstride, ldp, i / (size_t)ldp, i % (size_t)ldp, X[i]);
 }
 
+// Workgroups of the split-operand step: as many as are co-resident, at most
+// L.lp_groups (the workspace holds 2 G partial 128-tiles).
 template <class C>
-static hipError_t launch_lp_cfg(const Layout& L, const void* Pin_, void* Pout_, double* X,
-                                State* st, double* part, double* scratch, unsigned* cnt, int step,
-                                hipStream_t s) {
-    const typename C::Elem* Pin = (const typename C::Elem*)Pin_;
-    typename C::Elem* Pout = (typename C::Elem*)Pout_;
+static hipError_t lp_groups_cfg(const Layout& L, int* G) {
     static int per_cu = -1;
     static int cus = 0;
     if (per_cu < 0) {
@@ -478,15 +476,23 @@ static hipError_t launch_lp_cfg(const Layout& L, const void* Pin_, void* Pout_, 
         if (e != hipSuccess) return e;
         per_cu = nb < 1 ? 1 : nb;
     }
+    int g = per_cu * cus;
+    if (g > L.lp_groups) g = L.lp_groups;
+    *G = g < 1 ? 1 : g;
+    return hipSuccess;
+}
+
+template <class C>
+static hipError_t launch_lp_cfg(const Layout& L, const void* Pin_, void* Pout_, double* X,
+                                State* st, double* part, double* scratch, int step, hipStream_t s) {
+    const typename C::Elem* Pin = (const typename C::Elem*)Pin_;
+    typename C::Elem* Pout = (typename C::Elem*)Pout_;
+    int G = 0;
+    hipError_t e = lp_groups_cfg<C>(L, &G);
+    if (e != hipSuccess) return e;
     const int T = L.ldp / C::BT;
-    int G = per_cu * cus;
-    if (G > L.lp_groups) G = L.lp_groups;   // the workspace holds 2 G partial 128-tiles and G counters
-    if (G < 1) G = 1;
     hipLaunchKernelGGL(k_syrk_lp<C>, dim3(G), dim3(C::NT), C::LDS, s, Pin, Pout, L.plane_stride, X,
                        L.ldp, T, st, part, scratch, step);
-    const PlaneIO<C::MODE> io{Pin, Pout, L.plane_stride, L.ldp};
-    hipLaunchKernelGGL((k_sk_finish<C::BT, PlaneIO<C::MODE>, true>), dim3(sk_finish_grid(T * (T + 1) / 2, G, C::BT)),
-                       dim3(kFixThreads), 0, s, io, L.ldp, T, C::KE, st, part, scratch, (unsigned)G, step);
     return hipGetLastError();
 }
 
@@ -494,19 +500,23 @@ static hipError_t launch_lp_cfg(const Layout& L, const void* Pin_, void* Pout_, 
 template <int MODE> using LpMain = LpCfg<kLpTile, 2, 4, MODE>;
 
 hipError_t launch_syrk_lp(const Layout& L, sp2_compute mode, const void* Pin, void* Pout,
-                          double* X, State* st, double* part, double* scratch, unsigned* cnt,
-                          int step, hipStream_t s) {
+                          double* X, State* st, double* part, double* scratch, int step, hipStream_t s) {
     switch (mode) {
-        case SP2_C_F16X2:
-            return launch_lp_cfg<LpMain<SP2_C_F16X2>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
-        case SP2_C_BF16X3:
-            return launch_lp_cfg<LpMain<SP2_C_BF16X3>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
-        case SP2_C_BF16X2:
-            return launch_lp_cfg<LpMain<SP2_C_BF16X2>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
-        case SP2_C_FP8:
-            return launch_lp_cfg<LpMain<SP2_C_FP8>>(L, Pin, Pout, X, st, part, scratch, cnt, step, s);
-        default:
-            return hipErrorInvalidValue;
+        case SP2_C_F16X2: return launch_lp_cfg<LpMain<SP2_C_F16X2>>(L, Pin, Pout, X, st, part, scratch, step, s);
+        case SP2_C_BF16X3: return launch_lp_cfg<LpMain<SP2_C_BF16X3>>(L, Pin, Pout, X, st, part, scratch, step, s);
+        case SP2_C_BF16X2: return launch_lp_cfg<LpMain<SP2_C_BF16X2>>(L, Pin, Pout, X, st, part, scratch, step, s);
+        case SP2_C_FP8: return launch_lp_cfg<LpMain<SP2_C_FP8>>(L, Pin, Pout, X, st, part, scratch, step, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t lp_step_groups(const Layout& L, sp2_compute mode, int* G) {
+    switch (mode) {
+        case SP2_C_F16X2: return lp_groups_cfg<LpMain<SP2_C_F16X2>>(L, G);
+        case SP2_C_BF16X3: return lp_groups_cfg<LpMain<SP2_C_BF16X3>>(L, G);
+        case SP2_C_BF16X2: return lp_groups_cfg<LpMain<SP2_C_BF16X2>>(L, G);
+        case SP2_C_FP8: return lp_groups_cfg<LpMain<SP2_C_FP8>>(L, G);
+        default: return hipErrorInvalidValue;
     }
 }
 
