@@ -43,10 +43,22 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# Sources a step's kernels are compiled from (step kernel, step end, headers).
+STEP_SOURCES = {
+    "syrk_f64.hip": ["syrk_f64.hip", "syrk_f64_core.h", "sk_finish.h", "step_end.hip", "sp2_device.h",
+                     "sp2_internal.h"],
+    "syrk_lp.hip": ["syrk_lp.hip", "syrk_f64_core.h", "sk_finish.h", "step_end.hip", "sp2_device.h",
+                    "sp2_internal.h"],
+}
+
+
 def kernel_sha(name):
-    path = os.path.join(ROOT, "paper_2401_13772_amd", "csrc", name)
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 prefix over the sources of a step's kernels, in a fixed order."""
+    h = hashlib.sha256()
+    for src in STEP_SOURCES.get(name, [name]):
+        with open(os.path.join(ROOT, "paper_2401_13772_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(kernel_file, workload):
@@ -163,9 +175,13 @@ def timed_solves(sp2, H, D, ws, n_occ, args, compute, steps, warmup, stream):
 
 
 def kernel_lines(kern, n, elapsed, compute):
+    """Per step kind: the step kernel plus the step end (split-tile finish and
+    steering) that follows it, timed together by the library's HIP events."""
     flops_per_sq = float(n) * n * (n + 1)
-    kinds = {"f64": ("k_syrk_f64", PEAKS_TFLOPS["f64"], 1),
-             "split": ("k_syrk_lp", PEAKS_TFLOPS["fp8" if compute == "fp8" else "f16"], PRODUCTS[compute])}
+    f64_step = "k_syrk_f64_hyb + k_step_finish + k_step_steer" if n > 2048 else "k_syrk_f64"
+    kinds = {"f64": (f64_step, PEAKS_TFLOPS["f64"], 1),
+             "split": ("k_syrk_lp + k_step_finish + k_step_steer", PEAKS_TFLOPS["fp8" if compute == "fp8" else "f16"],
+                       PRODUCTS[compute])}
     lines = {}
     for key, (ms_tot, launches) in kern.items():
         if launches == 0:
