@@ -17,8 +17,7 @@
 // the whole tile), applies the SP2 update to its rows and to the mirrored
 // columns, and stores its sums in `part` after the whole tiles'.
 // k_step_steer: one workgroup adds `part` in index order and steers.
-// Both serve whichever step ran (split-operand in phase 1, FP64 otherwise);
-// a 64-tile FP64 step steers itself and they return at once.
+// Both serve whichever step ran (split-operand in phase 1, FP64 otherwise).
 #pragma once
 
 #include "syrk_f64_core.h"
@@ -272,13 +271,15 @@ __device__ void sk_fix_block(const IO& io, int ldp, int T, int KE, unsigned G, u
     (void)R;
 }
 
-// The two 128-tile step shapes a solve may run: split-operand (T_lp tiles a
-// side, G_lp workgroups, K slices of KE_lp) and FP64 (T_f64, G_f64, kBK;
-// G_f64 = 0 when the FP64 step is the self-steering 64-tile kernel).
+// The step shapes a solve may run: split-operand (T_lp 128-tiles a side,
+// G_lp workgroups, K slices of KE_lp) and FP64 (T_f64 tiles a side, G_f64
+// workgroups, kBK).  f64_small: the FP64 step is the 64-tile kernel, which
+// finishes its split tiles itself (it has none when every tile gets its own
+// workgroup) and leaves one sum per tile.
 struct StepShape {
     int ldp;
     int T_lp, KE_lp, G_lp;
-    int T_f64, G_f64;
+    int T_f64, G_f64, f64_small;
 };
 
 // Blocks of the split tiles of a step over T x T tiles on G workgroups.

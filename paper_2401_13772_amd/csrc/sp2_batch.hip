@@ -10,9 +10,13 @@
 //                        order as the single-matrix kernels;
 //   k_batch_step<C>      one SP2 step of every matrix still running: one
 //                        workgroup per (matrix, lower tile) item, the FP64 MFMA
-//                        tile and fused epilogue of syrk_f64_core.h, per-matrix
-//                        tile sums and steering by the matrix's last-arriving
-//                        workgroup;
+//                        tile and fused epilogue of syrk_f64_core.h, per-tile
+//                        sums, no cross-workgroup fence or counter;
+//   k_batch_steer<C>     after each step, one workgroup per matrix: the
+//                        matrix's tile sums in tile order and its steering
+//                        (the kernel boundary orders the step's writes; an
+//                        in-kernel arrival fence per item measured 3x the
+//                        whole batched solve's time);
 //   k_batch_finalize     D of every matrix;
 //   k_batch_info         the per-matrix sp2_info records.
 // The plan captures reset, bounds/init, max_iter steps, finalize and info
@@ -168,7 +172,6 @@ __global__ __launch_bounds__(C::NT) void k_batch_step(const BatchMat* __restrict
                                                       const double* __restrict__ coef, int step) {
     extern __shared__ double smem[];
     __shared__ double red[C::NW];
-    __shared__ int flag;
     const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];
     if (it.x < 0) return;
     const BatchMat& M = mats[it.x];
@@ -178,8 +181,6 @@ __global__ __launch_bounds__(C::NT) void k_batch_step(const BatchMat* __restrict
     const int ldp = M.ldp;
     const double* X = (st->restart_step == step) ? M.xk : ((step & 1) ? M.x1 : M.x0);
     double* Y = (step & 1) ? M.x0 : M.x1;
-    const int T = ldp / C::BT;
-    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
     const int KT = ldp / kBK;
     const unsigned t = (unsigned)it.y;
     int ti, tj;
@@ -211,17 +212,31 @@ __global__ __launch_bounds__(C::NT) void k_batch_step(const BatchMat* __restrict
         part[4 * t + 1] = trp;
         part[4 * t + 2] = fro;
     }
-    if (!group_arrive_last(&st->ticket, ntiles, &flag)) return;
+}
+
+// Steering of every matrix whose step `step` just ran: its tile sums in tile
+// order, with the same threads and order as the single-matrix kernel's last
+// workgroup (so a plan with that kernel's tile shape steers bit for bit like
+// sp2_density).  grid = matrices.
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_batch_steer(const BatchMat* __restrict__ mats, int step) {
+    __shared__ double red[C::NW];
+    const BatchMat& M = mats[blockIdx.x];
+    State* st = M.st;
+    if (st->done || st->iterations != step || st->phase == 1) return;
+    const int T = M.ldp / C::BT;
+    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
+    const int tid = threadIdx.x;
     double E = 0.0, TR = 0.0, F = 0.0;
     for (unsigned k = tid; k < ntiles; k += C::NT) {
-        E += part[4 * k + 0];
-        TR += part[4 * k + 1];
-        F += part[4 * k + 2];
+        E += M.part[4 * k + 0];
+        TR += M.part[4 * k + 1];
+        F += M.part[4 * k + 2];
     }
     E = group_sum<C::NW>(E, red);
     TR = group_sum<C::NW>(TR, red);
     F = group_sum<C::NW>(F, red);
-    if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
+    if (tid == 0) sp2_steer_thread0(st, E, TR, F, st->grow);
 }
 
 template <typename T>
@@ -279,14 +294,18 @@ hipError_t prepare_cfg() {
                                (int)C::LDS);
 }
 
-hipError_t launch_batch_step(int cfg, const BatchMat* mats, const int2* items, const double* coef,
+// One grouped step, then the steering of each of the nmats matrices.
+hipError_t launch_batch_step(int cfg, const BatchMat* mats, int nmats, const int2* items, const double* coef,
                              int nblocks, int step, hipStream_t s) {
-    if (cfg == 0)
+    if (cfg == 0) {
         hipLaunchKernelGGL(k_batch_step<BCfg64>, dim3(nblocks), dim3(BCfg64::NT), BCfg64::LDS, s, mats,
                            items, coef, step);
-    else
+        hipLaunchKernelGGL(k_batch_steer<BCfg64>, dim3(nmats), dim3(BCfg64::NT), 0, s, mats, step);
+    } else {
         hipLaunchKernelGGL(k_batch_step<BCfg32>, dim3(nblocks), dim3(BCfg32::NT), BCfg32::LDS, s, mats,
                            items, coef, step);
+        hipLaunchKernelGGL(k_batch_steer<BCfg32>, dim3(nmats), dim3(BCfg32::NT), 0, s, mats, step);
+    }
     return hipGetLastError();
 }
 
@@ -416,7 +435,7 @@ hipError_t enqueue_solve(sp2_plan* p, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int step = 0; step < p->max_iter; ++step) {
-        e = launch_batch_step(p->cfg, p->d_mats, p->d_items, p->d_coef, p->nblocks, step, s);
+        e = launch_batch_step(p->cfg, p->d_mats, p->batch, p->d_items, p->d_coef, p->nblocks, step, s);
         if (e != hipSuccess) return e;
     }
     if (p->dtype == SP2_F64)
@@ -446,7 +465,7 @@ hipError_t time_cfg(sp2_plan* p, const std::vector<int2>& items, int2* d_items_t
         hipLaunchKernelGGL(k_batch_reset, dim3((p->batch + tb - 1) / tb), dim3(tb), 0, s, p->d_mats,
                            p->batch, p->tol, 1, -1, 0.0);
         (void)hipEventRecord(a, s);
-        e = launch_batch_step(cfg, p->d_mats, d_items_tmp, p->d_coef, (int)items.size(), 0, s);
+        e = launch_batch_step(cfg, p->d_mats, p->batch, d_items_tmp, p->d_coef, (int)items.size(), 0, s);
         (void)hipEventRecord(b, s);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float ms = 0.f;

@@ -11,7 +11,7 @@ __global__ __launch_bounds__(kFixThreads) void k_step_finish(PlaneIO<MODE> lio, 
                                                              const double* __restrict__ scratch, int step) {
     if (st->done || st->iterations != step) return;
     const bool lp = st->phase == 1;
-    if (!lp && sh.G_f64 == 0) return;
+    if (!lp && sh.f64_small) return;
     const int grow = st->grow;
     if (lp) {
         if (blockIdx.x >= sk_fix_blocks(sh.T_lp, sh.G_lp)) return;
@@ -27,8 +27,9 @@ __global__ __launch_bounds__(kFixThreads) void k_step_steer(StepShape sh, State*
     __shared__ double red[kFixThreads / 64];
     if (st->done || st->iterations != step) return;
     const bool lp = st->phase == 1;
-    if (!lp && sh.G_f64 == 0) return;
-    const unsigned entries = lp ? sk_entries(sh.T_lp, sh.G_lp) : sk_entries(sh.T_f64, sh.G_f64);
+    const unsigned entries = lp ? sk_entries(sh.T_lp, sh.G_lp)
+                                : sh.f64_small ? (unsigned)(sh.T_f64 * (sh.T_f64 + 1) / 2)
+                                               : sk_entries(sh.T_f64, sh.G_f64);
     sk_steer(st, part, entries, st->grow, red);
 }
 
@@ -38,7 +39,7 @@ static hipError_t step_end_t(const Layout& L, const StepShape& sh, const void* P
     typedef typename Planes<MODE>::Elem E;
     const PlaneIO<MODE> lio{(const E*)Pin, (E*)Pout, L.plane_stride, L.ldp};
     const F64IO fio{X, Y, L.ldp};
-    const unsigned lb = sk_fix_blocks(sh.T_lp, sh.G_lp), fb = sk_fix_blocks(sh.T_f64, sh.G_f64);
+    const unsigned lb = sk_fix_blocks(sh.T_lp, sh.G_lp), fb = sh.f64_small ? 0u : sk_fix_blocks(sh.T_f64, sh.G_f64);
     const unsigned grid = lb > fb ? lb : fb;
     if (grid > 0)
         hipLaunchKernelGGL(k_step_finish<MODE>, dim3(grid), dim3(kFixThreads), 0, s, lio, fio, sh, st, part,
@@ -54,14 +55,14 @@ hipError_t launch_step_end(const Layout& L, sp2_compute mode, const void* Pin, v
     sh.ldp = L.ldp;
     hipError_t e = f64_step_groups(L, &sh.G_f64);
     if (e != hipSuccess) return e;
-    sh.T_f64 = L.ldp / kLpTile;
+    sh.f64_small = L.bt != kLpTile;
+    sh.T_f64 = L.ldp / L.bt;
     if (L.np > 0) {
         e = lp_step_groups(L, mode, &sh.G_lp);
         if (e != hipSuccess) return e;
         sh.T_lp = L.ldp / kLpTile;
         sh.KE_lp = 64 / L.pb;
     }
-    if (sh.G_f64 == 0 && sh.G_lp == 0) return hipSuccess;   // nothing of a 128-tile step to end
     switch (L.np > 0 ? mode : SP2_C_F16X2) {   // an FP64-only solve never reads planes
         case SP2_C_F16X2: return step_end_t<SP2_C_F16X2>(L, sh, Pin, Pout, X, Y, st, part, scratch, step, s);
         case SP2_C_BF16X3: return step_end_t<SP2_C_BF16X3>(L, sh, Pin, Pout, X, Y, st, part, scratch, step, s);

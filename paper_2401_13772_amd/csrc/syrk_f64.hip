@@ -5,7 +5,8 @@
 //     e^2  += (S - X)^2        idempotency of X_m, for the stop test
 //     X'    = S or 2X - S      the branch chosen by tr X_m vs n_occ
 //     tr   += X'_ii, ||X'||^2  for the next branch decision
-//   and the steering of the next step, taken on the device by the last block.
+//   and the steering of the next step, taken on the device by k_step_steer
+//   (step_end.hip), launched after the step.
 //
 // Design for CDNA4:
 //   * only the lower block-triangle of BT x BT tiles is computed (X X^T is
@@ -30,8 +31,9 @@
 //   * workgroups are renumbered so each XCD (blocks are dealt round-robin to
 //     the 8 XCDs) works on a contiguous run of tiles, which share row panels
 //     in that XCD's L2;
-//   * per-tile sums go to a partial buffer that the last-arriving workgroup
-//     adds in tile order: deterministic, no floating-point atomics.
+//   * per-tile sums go to a partial buffer that k_step_steer adds in tile
+//     order after the kernel: deterministic, no floating-point atomics, and
+//     no arrival fence (an L2 write-back on every XCD) in the step kernel.
 #include "sk_finish.h"
 
 namespace sp2 {
@@ -120,17 +122,6 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64(const double* __restrict__ X
             part[4 * t + 2] = fro;
         }
     }
-    if (!group_arrive_last(&st->ticket, G, &flag)) return;
-    double E = 0.0, TR = 0.0, F = 0.0;
-    for (unsigned k = tid; k < ntiles; k += C::NT) {
-        E += part[4 * k + 0];
-        TR += part[4 * k + 1];
-        F += part[4 * k + 2];
-    }
-    E = group_sum<C::NW>(E, red);
-    TR = group_sum<C::NW>(TR, red);
-    F = group_sum<C::NW>(F, red);
-    if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
 }
 
 // ---------------------------------------------------------------- 128-tile kernel
@@ -318,7 +309,7 @@ hipError_t launch_syrk_f64(const Layout& L, const double* X, double* Y, State* s
 }
 
 hipError_t f64_step_groups(const Layout& L, int* G) {
-    if (L.bt == CfgSmall::BT) {   // the 64-tile kernel steers itself
+    if (L.bt == CfgSmall::BT) {   // the 64-tile kernel: no remainder for the step end to finish
         *G = 0;
         return hipSuccess;
     }
