@@ -18,8 +18,10 @@
 //     whether X' has a nonzero (the new flag);
 //   * a tile with no product and a zero X tile is X' = 0: it is only written
 //     (as zeros) when the output buffer's tile held a nonzero;
-//   * per-tile sums go to fixed slots and the last-arriving workgroup adds
-//     them in tile order and steers (sp2_steer_thread0), as the dense step.
+//   * per-tile sums go to fixed slots; k_sparse_steer, launched after the
+//     step, adds them in tile order and steers (sp2_steer_thread0), so the
+//     step needs no arrival fence (an L2 write-back on every XCD, paid by
+//     each of its workgroups).
 #include <cmath>
 
 #include "syrk_f64_core.h"
@@ -65,13 +67,11 @@ __global__ __launch_bounds__(C::NT, 2) void k_sparse_step(const double* __restri
                                                        int step) {
     extern __shared__ __attribute__((aligned(16))) char lsm[];
     __shared__ double red[C::NW];
-    __shared__ int flag;
     __shared__ int s_nz;
     __shared__ unsigned char act[kSpMaxT];
     if (st->done || st->iterations != step) return;
     const int grow = st->grow;
     const int tid = threadIdx.x;
-    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     int ti, tj;
     grouped_tile(t, T, kSpGroupM, ti, tj);
@@ -130,7 +130,17 @@ __global__ __launch_bounds__(C::NT, 2) void k_sparse_step(const double* __restri
         if (slices) atomicAdd(&st->sp_slices, (unsigned long long)slices);
         if (any || xnz) atomicAdd(&st->sp_tiles, 1ull);
     }
-    if (!group_arrive_last(&st->ticket, ntiles, &flag)) return;
+}
+
+// The steering of step `step`: the step's tile sums in tile order.  One
+// workgroup.
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_sparse_steer(State* st, const double* __restrict__ part, int T,
+                                                        int step) {
+    __shared__ double red[C::NW];
+    if (st->done || st->iterations != step) return;
+    const unsigned ntiles = (unsigned)(T * (T + 1) / 2);
+    const int tid = threadIdx.x;
     double E = 0.0, TR = 0.0, F = 0.0;
     for (unsigned k = tid; k < ntiles; k += C::NT) {
         E += part[4 * k + 0];
@@ -140,7 +150,7 @@ __global__ __launch_bounds__(C::NT, 2) void k_sparse_step(const double* __restri
     E = group_sum<C::NW>(E, red);
     TR = group_sum<C::NW>(TR, red);
     F = group_sum<C::NW>(F, red);
-    if (tid == 0) sp2_steer_thread0(st, E, TR, F, grow);
+    if (tid == 0) sp2_steer_thread0(st, E, TR, F, st->grow);
 }
 
 // Workspace: state | pair/tile partials | row partials | flags x 2 | X0 | X1.
@@ -249,6 +259,7 @@ int sp2_density_sparse(const void* H, void* D, int n, int ld, int n_occ, double 
             const int odd = issued & 1;
             hipLaunchKernelGGL(k_sparse_step<C>, dim3(SL.tiles), dim3(C::NT), lds, s, xb[odd], xb[odd ^ 1], SL.ldp,
                                SL.T, st, part, flags[odd], flags[odd ^ 1], tau, issued);
+            hipLaunchKernelGGL(k_sparse_steer<C>, dim3(1), dim3(C::NT), 0, s, st, part, SL.T, issued);
             SP2_SP_HIP(hipGetLastError());
         }
         lease.pending = s;
