@@ -110,7 +110,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_bounds_init(const BatchMat* 
         pair_row_partials(n, I, J, sA, sB, M.rowpart, ldp);
     }
     if (bad) atomicOr(&sbad, 1);
-    __threadfence();
+    // one workgroup per matrix: the barrier's workgroup-scope fence makes the
+    // row partials (global memory) visible to its other threads; an
+    // agent-scope fence here would write back and invalidate the L2s
     __syncthreads();
     double lo = INFINITY, hi = -INFINITY;
     for (int i = tid; i < n; i += kThreads) {
@@ -150,8 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_bounds_init(const BatchMat* 
         const size_t q = (size_t)ldp * ldp / 4;
         for (size_t i = tid; i < q; i += kThreads) ((d4*)M.xk)[i] = ((const d4*)M.x0)[i];
     }
-    __threadfence();
-    __syncthreads();
+    __syncthreads();   // the pair sums, read by this workgroup only
     double t = 0.0, f = 0.0;
     for (unsigned k = tid; k < npairs; k += kThreads) {
         t += M.part[2 * k + 0];
