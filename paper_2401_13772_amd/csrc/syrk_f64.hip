@@ -137,8 +137,9 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64(const double* __restrict__ X
 // The kernels launched after it (k_step_finish, k_step_steer) add a split
 // tile's partials in workgroup order (the sum does not depend on which segment
 // finished last), run the split tiles' epilogue and take the steering
-// decision: this kernel needs no fence or counter between its workgroups.  The remainder runs
-// before the waves, so its partial stores do not trail the waves.
+// decision: this kernel needs no fence or counter between its workgroups.
+// Even XCDs run the remainder before their waves, odd XCDs after, so the
+// tile epilogues of the two halves (HBM-bound bursts) do not coincide.
 constexpr int kGroupM = 8;
 
 template <class C>
@@ -176,60 +177,72 @@ __global__ __launch_bounds__(C::NT) void k_syrk_f64_hyb(const double* __restrict
     // leaves its FP64 partial tile, row-major, in slot 2g (the range's first
     // tile) or 2g + 1; k_step_finish adds them after this kernel.  R < G <= 1024
     // and KT <= 4096 keep every product below 2^32 (32-bit range arithmetic).
-    if (R > 0) {
-        const SkSplit sk(R, (unsigned)KT, G);
-        // remainder owners by hardware block index: blocks are dealt round-robin
-        // to the XCDs, so the owners spread over all of them
-        const unsigned gr = blockIdx.x;
-        unsigned u, u1;
-        sk.range(gr, u, u1);
-        int seg_no = 0;
-        const int lane = tid & 63, w = tid >> 6;
-        const int wm = w / C::WN, wn = w % C::WN;
-        while (u < u1) {
-            const unsigned r = u / (unsigned)KT;
-            const int k0 = (int)(u - r * (unsigned)KT);
-            const unsigned kend = (unsigned)k0 + (u1 - u);
-            const int k1 = kend < (unsigned)KT ? (int)kend : KT;
+    auto remainder = [&]() {
+        if (R > 0) {
+            const SkSplit sk(R, (unsigned)KT, G);
+            // remainder owners by hardware block index: blocks are dealt round-robin
+            // to the XCDs, so the owners spread over all of them
+            const unsigned gr = blockIdx.x;
+            unsigned u, u1;
+            sk.range(gr, u, u1);
+            int seg_no = 0;
+            const int lane = tid & 63, w = tid >> 6;
+            const int wm = w / C::WN, wn = w % C::WN;
+            while (u < u1) {
+                const unsigned r = u / (unsigned)KT;
+                const int k0 = (int)(u - r * (unsigned)KT);
+                const unsigned kend = (unsigned)k0 + (u1 - u);
+                const int k1 = kend < (unsigned)KT ? (int)kend : KT;
+                int ti, tj;
+                grouped_tile(Dt + r, T, kGroupM, ti, tj);
+                d4 acc[C::MI][C::NI];
+#pragma unroll
+                for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
+                if (ti == tj) syrk_mainloop_dma<C, true>(X, ldp, ti, tj, k0, k1, lsm, acc);
+                else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, k0, k1, lsm, acc);
+                u += (unsigned)(k1 - k0);
+                double* mine = scratch + (2 * (size_t)gr + seg_no++) * (size_t)C::BT * C::BT;
+                // accumulator (mi, ni, r) of a lane: row 16 mi + lane / 16 + 4 r of
+                // the wave's sub-tile, column 16 ni + lane % 16
+#pragma unroll
+                for (int mi = 0; mi < C::MI; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < C::NI; ++ni)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int row = wm * C::WTM + mi * 16 + (lane >> 4) + 4 * q;
+                            const int col = wn * C::WTN + ni * 16 + (lane & 15);
+                            mine[row * C::BT + col] = acc[mi][ni][q];
+                        }
+            }
+        }
+    };
+    auto waves_part = [&]() {
+        // data-parallel waves
+        for (unsigned w = 0; w < waves; ++w) {
+            const unsigned t = w * G + g;
             int ti, tj;
-            grouped_tile(Dt + r, T, kGroupM, ti, tj);
+            grouped_tile(t, T, kGroupM, ti, tj);
             d4 acc[C::MI][C::NI];
 #pragma unroll
             for (int mi = 0; mi < C::MI; ++mi)
 #pragma unroll
                 for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
-            if (ti == tj) syrk_mainloop_dma<C, true>(X, ldp, ti, tj, k0, k1, lsm, acc);
-            else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, k0, k1, lsm, acc);
-            u += (unsigned)(k1 - k0);
-            double* mine = scratch + (2 * (size_t)gr + seg_no++) * (size_t)C::BT * C::BT;
-            // accumulator (mi, ni, r) of a lane: row 16 mi + lane / 16 + 4 r of
-            // the wave's sub-tile, column 16 ni + lane % 16
-#pragma unroll
-            for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < C::NI; ++ni)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int row = wm * C::WTM + mi * 16 + (lane >> 4) + 4 * q;
-                        const int col = wn * C::WTN + ni * 16 + (lane & 15);
-                        mine[row * C::BT + col] = acc[mi][ni][q];
-                    }
+            if (ti == tj) syrk_mainloop_dma<C, true>(X, ldp, ti, tj, 0, KT, lsm, acc);
+            else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, 0, KT, lsm, acc);
+            finish(t, ti, tj, acc);
         }
-    }
-
-    // data-parallel waves
-    for (unsigned w = 0; w < waves; ++w) {
-        const unsigned t = w * G + g;
-        int ti, tj;
-        grouped_tile(t, T, kGroupM, ti, tj);
-        d4 acc[C::MI][C::NI];
-#pragma unroll
-        for (int mi = 0; mi < C::MI; ++mi)
-#pragma unroll
-            for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
-        if (ti == tj) syrk_mainloop_dma<C, true>(X, ldp, ti, tj, 0, KT, lsm, acc);
-        else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, 0, KT, lsm, acc);
-        finish(t, ti, tj, acc);
+    };
+    // Blocks are dealt round-robin to the 8 XCDs, so a block's index parity is
+    // its XCD's: even XCDs run their remainder share before their waves, odd
+    // XCDs after.  The two halves' tile epilogues (HBM-bound bursts of X reads
+    // and X' writes) then come at different times instead of all at once.
+    const bool remainder_first = (blockIdx.x & 1) == 0;
+    for (int half = 0; half < 2; ++half) {
+        if ((half == 0) == remainder_first) remainder();
+        else waves_part();
     }
 }
 

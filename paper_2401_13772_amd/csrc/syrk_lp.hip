@@ -36,7 +36,8 @@
 //   * the schedule of the 128-tile FP64 step: grouped raster, K-synchronous
 //     data-parallel waves (the workgroups of one XCD share panels in L2) and
 //     a stream-K remainder whose FP64 partial tiles k_step_finish adds in a
-//     fixed order.
+//     fixed order, run before the waves on even XCDs and after them on odd
+//     ones.
 #include "sk_finish.h"
 
 namespace sp2 {
@@ -404,43 +405,55 @@ __global__ __launch_bounds__(C::NT) void k_syrk_lp(const typename C::Elem* __res
         }
     };
 
-    // stream-K remainder first (the split of SkSplit): each segment of a split
-    // tile leaves its FP64 partial tile in slot 2g (the range's first tile) or
-    // 2g + 1; k_step_finish adds them after this kernel.  Running the remainder
-    // before the data-parallel waves keeps its stores out of the waves' way.
-    if (R > 0) {
-        const SkSplit sk(R, (unsigned)KT, G);
-        // remainder owners by hardware block index: blocks are dealt round-robin
-        // to the XCDs, so the owners spread over all of them
-        const unsigned gr = blockIdx.x;
-        unsigned u, u1;
-        sk.range(gr, u, u1);
-        int seg_no = 0;
-        while (u < u1) {
-            const unsigned r = u / (unsigned)KT;
-            const int k0 = (int)(u - r * (unsigned)KT);
-            const unsigned kend = (unsigned)k0 + (u1 - u);
-            const int k1 = kend < (unsigned)KT ? (int)kend : KT;
-            int ti, tj;
-            grouped_tile(Dt + r, T, 8, ti, tj);
-            run(ti, tj, k0, k1);
-            u += (unsigned)(k1 - k0);
-            d2* mine = (d2*)(scratch + (2 * (size_t)gr + seg_no++) * (size_t)C::BT * C::BT);
-            for (int i = tid; i < C::BT * C::BT / 2; i += C::NT) {
-                const int e = 2 * i;
-                mine[i] = d2{Cs[(e / C::BT) * C::CLD + (e % C::BT)], Cs[(e / C::BT) * C::CLD + (e % C::BT) + 1]};
+    // stream-K remainder (the split of SkSplit): each segment of a split tile
+    // leaves its FP64 partial tile in slot 2g (the range's first tile) or
+    // 2g + 1; k_step_finish adds them after this kernel.
+    auto remainder = [&]() {
+        if (R > 0) {
+            const SkSplit sk(R, (unsigned)KT, G);
+            // remainder owners by hardware block index: blocks are dealt round-robin
+            // to the XCDs, so the owners spread over all of them
+            const unsigned gr = blockIdx.x;
+            unsigned u, u1;
+            sk.range(gr, u, u1);
+            int seg_no = 0;
+            while (u < u1) {
+                const unsigned r = u / (unsigned)KT;
+                const int k0 = (int)(u - r * (unsigned)KT);
+                const unsigned kend = (unsigned)k0 + (u1 - u);
+                const int k1 = kend < (unsigned)KT ? (int)kend : KT;
+                int ti, tj;
+                grouped_tile(Dt + r, T, 8, ti, tj);
+                run(ti, tj, k0, k1);
+                u += (unsigned)(k1 - k0);
+                d2* mine = (d2*)(scratch + (2 * (size_t)gr + seg_no++) * (size_t)C::BT * C::BT);
+                for (int i = tid; i < C::BT * C::BT / 2; i += C::NT) {
+                    const int e = 2 * i;
+                    mine[i] = d2{Cs[(e / C::BT) * C::CLD + (e % C::BT)], Cs[(e / C::BT) * C::CLD + (e % C::BT) + 1]};
+                }
+                __syncthreads();   // the next main loop refills this LDS
             }
-            __syncthreads();   // the next main loop refills this LDS
         }
-    }
-    // data-parallel waves over the grouped raster: the workgroups of one XCD
-    // run their tiles' K slices in step and share row and column panels in L2
-    for (unsigned w = 0; w < waves; ++w) {
-        const unsigned t = w * G + g;
-        int ti, tj;
-        grouped_tile(t, T, 8, ti, tj);
-        run(ti, tj, 0, KT);
-        finish(t, ti, tj);
+    };
+    auto waves_part = [&]() {
+        // data-parallel waves over the grouped raster: the workgroups of one XCD
+        // run their tiles' K slices in step and share row and column panels in L2
+        for (unsigned w = 0; w < waves; ++w) {
+            const unsigned t = w * G + g;
+            int ti, tj;
+            grouped_tile(t, T, 8, ti, tj);
+            run(ti, tj, 0, KT);
+            finish(t, ti, tj);
+        }
+    };
+    // Blocks are dealt round-robin to the 8 XCDs, so a block's index parity is
+    // its XCD's: even XCDs run their remainder share before their waves, odd
+    // XCDs after.  The two halves' tile epilogues (HBM-bound bursts of X reads
+    // and X' writes) then come at different times instead of all at once.
+    const bool remainder_first = (blockIdx.x & 1) == 0;
+    for (int half = 0; half < 2; ++half) {
+        if ((half == 0) == remainder_first) remainder();
+        else waves_part();
     }
 }
 
