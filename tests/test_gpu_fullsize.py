@@ -1,9 +1,10 @@
 """GPU parity at the benchmark's sizes, in the launch configuration bench.py
 times (same library entry point, same tile and stream-K choices).
 
-At n >= ~2900 the squaring kernel has more tiles than co-resident workgroups,
-so stream-K splits tiles between two workgroups; these tests are the ones
-that exercise that path.  The full solve is too slow for the oracle here, so
+Above n = 2048 the FP64 step uses 128-tiles: at n = 2176 (153 lower tiles,
+fewer than the co-resident workgroups) every tile is split stream-K and
+finished by the step-end kernel; at n = 3000 and 4096 whole-tile waves run
+beside a split remainder.  These tests are the ones that exercise that path.  The full solve is too slow for the oracle here, so
 we check (a) one step entry by entry against the oracle, (b) the final D
 against a third-party FP64 eigendecomposition (LAPACK through NumPy) and the
 properties of a projector.  Tolerances: FP64 storage 1e-10 rms; FP32 storage
@@ -31,7 +32,7 @@ def lapack_dm(H, n_occ):
     return V[:, :n_occ] @ V[:, :n_occ].T, w
 
 
-@pytest.mark.parametrize("n,dtype", [(3000, np.float64), (4096, np.float32)])
+@pytest.mark.parametrize("n,dtype", [(2176, np.float64), (3000, np.float64), (4096, np.float32)])
 def test_one_step_sampled_entries_split_tiles(sp2, oracle_lib, n, dtype):
     inst = make_tb_hamiltonian(n, seed=11, dtype=dtype)
     H64 = inst.H.astype(np.float64)

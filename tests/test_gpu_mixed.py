@@ -102,6 +102,34 @@ def test_single_split_step_entries(sp2, oracle_lib, mode, n):
     assert np.array_equal(D2, D2.T)
 
 
+@pytest.mark.parametrize("mode", ["f16x2", "bf16x3", "fp8"])
+def test_split_step_entries_every_tile_split(sp2, oracle_lib, mode):
+    """n = 2176 (17 x 17 tiles of 128, 153 lower tiles): fewer tiles than the
+    step kernels' workgroups, so every tile of the FP64 step and of the
+    split-operand step is a stream-K remainder tile, finished by the step-end
+    kernel from its workgroups' FP64 partials (planes of 2 bytes or, for FP8,
+    1 byte).  One FP64 step, then one split-operand step, entry by entry,
+    including whole tile rows at the tile edges."""
+    n = 2176
+    inst = make_tb_hamiltonian(n, seed=5)
+    D2, info = solve(sp2, inst.H, inst.n_occ, compute=mode, fp64_prefix_iters=1, max_iter=2)
+    assert info.status == 1 and info.iterations == 2 and info.fp64_prefix_iters == 1
+    r1 = oracle_lib.sp2(inst.H, inst.n_occ, max_iter=1)
+    X1 = r1.D
+    grow = int(np.trace(X1) - inst.n_occ <= 0)
+    assert info.branches() == [r1.branches()[0], grow]
+    rng = np.random.default_rng(4)
+    edge = np.concatenate([np.arange(120, 136), np.arange(n - 16, n)])
+    I = np.concatenate([rng.integers(0, n, 3000), np.repeat(edge, 64), np.arange(n)])
+    J = np.concatenate([rng.integers(0, n, 3000), np.tile(rng.integers(0, n, 64), edge.size), np.arange(n)[::-1]])
+    want = oracle_lib.sp2_step_entries(X1, grow, I, J)
+    absX = np.abs(X1)
+    scale, floor = (2.0 ** -6, 1e-6) if mode == "fp8" else (2.0 ** -18, 1e-9)
+    bound = scale * np.einsum("tk,tk->t", absX[I], absX[J]) + floor
+    assert np.all(np.abs(D2[I, J] - want) <= bound)
+    assert np.array_equal(D2, D2.T)
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_mixed_fullsize_split_tiles(sp2, mode):
     """n = 4096, FP32 storage: the bench workload, stream-K split tiles in both
