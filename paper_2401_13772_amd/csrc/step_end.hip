@@ -1,6 +1,7 @@
-// step_end.hip -- launches of the kernels that end one SP2 step of the
-// single-matrix solve (sk_finish.h): the split tiles of the step's stream-K
-// remainder, then the steering of the next step.
+// step_end.hip -- the kernels that end one SP2 step of the single-matrix
+// solve, and their launch: k_step_finish completes the split tiles of the
+// step's stream-K remainder (sk_fix_block of sk_finish.h), k_step_steer adds
+// the step's per-tile sums and steers the next step.
 #include "sk_finish.h"
 
 namespace sp2 {
