@@ -127,9 +127,9 @@ size_t sp2_workspace_size(int n, sp2_dtype dtype, sp2_compute compute);
  *                    gap around the Fermi level is still small in the mapped
  *                    spectrum and rounding errors would be amplified;
  *                 2. trace-steered steps with split-operand 16-bit products
- *                    and FP32 accumulation (traces and norms in FP64) until
- *                    the idempotency stops decreasing over two steps from a
- *                    value below 0.1;
+ *                    and FP32 accumulation (traces and norms in FP64) until,
+ *                    from a value below 0.1, the idempotency no longer drops
+ *                    tenfold over two steps (the rounding floor);
  *                 3. FP64 refinement steps alternating X^2 and 2X - X^2
  *                    (not steered by the trace) until e <= tol, at most 8.
  *               info->fp64_prefix_iters and info->refine_steps report 1 and 3.

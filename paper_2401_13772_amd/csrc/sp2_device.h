@@ -416,11 +416,15 @@ __device__ __forceinline__ void sp2_steer_thread0(State* st, double E, double TR
         st->lp_mask[m >> 6] |= 1ull << (m & 63);
         st->lp_steps = st->lp_steps + 1;
         st->grow = trace_grow;
-        // the rounding floor: no progress over two steps from below 0.1.  The
-        // earlier value decides, so that a run-away from the floor (FP8 at
+        // the rounding floor: from below 0.1, e no longer drops tenfold over two
+        // steps (below 0.1 a pair of exact steps takes e to ~0.4 e^2, so a
+        // ratio above 1/10 means the rounding level has been reached: at
+        // n = 4096 FP16x2, e goes 8.3e-3, 1.5e-5, 2.5e-5, 2.4e-6, 2.6e-6, ...).
+        // The earlier value decides, so that a run-away from the floor (FP8 at
         // n = 16384: e = 0.087, 0.154, 0.302, 0.6, ... as levels just outside
         // [0, 1] are squared) hands over as well
-        const bool floor_hit = (m - st->lp_start >= 2) && e >= st->e_hist[m - 2] && st->e_hist[m - 2] < 0.1;
+        const bool floor_hit =
+            (m - st->lp_start >= 2) && e >= 0.1 * st->e_hist[m - 2] && st->e_hist[m - 2] < 0.1;
         if (e <= st->tol) {
             st->done = 1;
             st->status = SP2_OK;
