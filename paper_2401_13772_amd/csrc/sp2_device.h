@@ -356,13 +356,14 @@ __device__ inline void state_after_init(State* st, double t, double f) {
 }
 
 // ---------------------------------------------------------------- steering
-// Run by one thread of the last-arriving workgroup after step m, with the
+// Run by one thread after step m (in the step's steering kernel, or in the
+// last-arriving workgroup of a kernel that reduces by arrival), with the
 // fixed-order sums E = ||S - X_m||^2, TR = tr X_{m+1}, F = ||X_{m+1}||^2.
 //   phase 0: FP64 steps steered by the trace (plain SP2, or the FP64 prefix of
 //            a mixed-precision solve, which hands over after m0 steps);
 //   phase 1: split-precision steps steered by the trace, until the
-//            idempotency stops improving (the rounding floor of the split
-//            products) -> phase 2;
+//            idempotency no longer drops tenfold over two steps (the
+//            rounding floor of the split products) -> phase 2;
 //   phase 2: FP64 refinement: x^2 and 2x - x^2 alternate regardless of the
 //            trace (a trace-steered continuation of a low-precision iterate
 //            can square an eigenvalue at 1 + eps away from 1), until e <= tol.

@@ -13,8 +13,10 @@ constexpr int kThreads = 256;        // every kernel uses 4 wave64s per workgrou
 constexpr int kBndTile = 64;         // tile edge of the bounds / init / finalize kernels
 constexpr int kMaxPersistent = 1024; // upper bound on the stream-K grid
 
-// Loop state, resident in the workspace.  Written by the last-arriving block
-// of each kernel; read by every kernel at start (kernel boundaries order it).
+// Loop state, resident in the workspace.  Written by one workgroup per kernel
+// (a step's steering kernel, or the last-arriving block of a kernel that
+// reduces by arrival); read by every kernel at start (kernel boundaries order
+// it).
 struct State {
     double emin, emax;
     double tr;          // trace of the current iterate X_m
@@ -29,7 +31,7 @@ struct State {
     int32_t iterations; // squarings done; X_m lives in buffer (m & 1)
     int32_t special;    // 1: n_occ == 0 -> D = 0; 2: n_occ == n -> D = I
     int32_t bad;        // a non-finite entry was seen in H
-    uint32_t ticket;    // arrival counter of the last-block reductions
+    uint32_t ticket;    // arrival counter of the kernels that reduce by arrival
     int32_t fp64_steps; // trace-steered FP64 steps (phase 0)
     // mixed precision: phase 0 = FP64 prefix, 1 = split-operand steps,
     // 2 = FP64 refinement (alternating x^2 / 2x - x^2)
