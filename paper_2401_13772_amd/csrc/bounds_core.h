@@ -37,16 +37,28 @@ __device__ inline void load_pair(const T* __restrict__ H, int n, int ld, int I, 
     const bool whole = (I + 1) * kBndTile <= n && (J + 1) * kBndTile <= n && (ld % V) == 0 &&
                        (reinterpret_cast<uintptr_t>(H) % 16) == 0;
     if (whole) {
-        // interior pair: 16-byte loads, the same values as the element loop
-        for (int e = threadIdx.x; e < kBndTile * VPR; e += kThreads) {
+        // interior pair: 16-byte loads, the same values as the element loop.
+        // Every load of the thread is issued before the first LDS store, so
+        // the block waits for one memory latency instead of one per trip.
+        constexpr int IT = kBndTile * VPR / kThreads;   // loads per thread and tile
+        static_assert(kBndTile * VPR % kThreads == 0, "tile must split evenly over the threads");
+        vec a[IT], b[IT];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            const int e = threadIdx.x + t * kThreads;
             const int rr = e / VPR, cv = (e % VPR) * V;
-            const vec a = *(const vec*)(H + (size_t)(I * kBndTile + rr) * ld + J * kBndTile + cv);
-            const vec b = *(const vec*)(H + (size_t)(J * kBndTile + rr) * ld + I * kBndTile + cv);
+            a[t] = *(const vec*)(H + (size_t)(I * kBndTile + rr) * ld + J * kBndTile + cv);
+            b[t] = *(const vec*)(H + (size_t)(J * kBndTile + rr) * ld + I * kBndTile + cv);
+        }
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            const int e = threadIdx.x + t * kThreads;
+            const int rr = e / VPR, cv = (e % VPR) * V;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                bad |= (int)!isfinite((double)a[v]) | (int)!isfinite((double)b[v]);
-                sA[rr][cv + v] = (L)a[v];
-                sB[rr][cv + v] = (L)b[v];
+                bad |= (int)!isfinite((double)a[t][v]) | (int)!isfinite((double)b[t][v]);
+                sA[rr][cv + v] = (L)a[t][v];
+                sB[rr][cv + v] = (L)b[t][v];
             }
         }
         return;

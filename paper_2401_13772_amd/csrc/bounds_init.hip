@@ -164,15 +164,25 @@ __global__ __launch_bounds__(kThreads) void k_finalize(T* __restrict__ D, int n,
     const E* psrc = (const E*)(odd ? p1 : p0);
     const bool from_planes = (MODE != SP2_C_F64) && st->stale;
     const int i = blockIdx.x;
-    for (int j = threadIdx.x; j < n; j += kThreads) {
-        double v;
-        const size_t idx = (size_t)i * ldp + j;
-        if (special == 1) v = 0.0;
-        else if (special == 2) v = (i == j) ? 1.0 : 0.0;
-        else if (from_planes) v = load_planes<PM>(psrc, pstride, ldp, (size_t)i, (size_t)j);
-        else v = src[idx];
-        D[(size_t)i * ld + j] = (T)v;
-    }
+    // U elements per thread and trip, all loaded before the first store (one
+    // memory latency per trip), then the row's tail one element at a time;
+    // one copy of the loop per source, so no branch sits between the loads
+    auto put = [&](auto&& value) {
+        constexpr int U = 8;
+        int j = threadIdx.x;
+        for (; j + (U - 1) * kThreads < n; j += U * kThreads) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = value(j + u * kThreads);
+#pragma unroll
+            for (int u = 0; u < U; ++u) D[(size_t)i * ld + j + u * kThreads] = (T)v[u];
+        }
+        for (; j < n; j += kThreads) D[(size_t)i * ld + j] = (T)value(j);
+    };
+    if (special == 1) put([](int) { return 0.0; });
+    else if (special == 2) put([&](int j) { return (i == j) ? 1.0 : 0.0; });
+    else if (from_planes) put([&](int j) { return load_planes<PM>(psrc, pstride, ldp, (size_t)i, (size_t)j); });
+    else put([&](int j) { return src[(size_t)i * ldp + j]; });
 }
 
 // ---------------------------------------------------------------- launchers
