@@ -45,20 +45,6 @@ __device__ inline double group_sum(double v, double* scratch) {
     return r;
 }
 
-// True in every thread of the one workgroup that arrives last.
-__device__ inline bool group_arrive_last(unsigned* ticket, unsigned nblocks, int* flag_lds) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(ticket, 1u);
-        *flag_lds = (t == nblocks - 1);
-    }
-    __syncthreads();
-    bool last = *flag_lds != 0;
-    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return last;
-}
-
 // ---------------------------------------------------------------- split planes
 // A value x (|x| <= 1 for SP2 iterates) is kept as a sum of 16-bit planes:
 //   F16X2 : x ~ h + 2^-11 l',  h = fp16(x), l' = fp16((x - h) 2^11)
