@@ -4,10 +4,12 @@
 //
 // Kernels (all grouped over the matrices of the plan):
 //   k_batch_reset        loop state of every matrix;
-//   k_batch_bounds_init  one workgroup per matrix: Gershgorin bounds of
-//                        (H + H^T)/2 and X_0 with its trace (Section "SP2
-//                        solver", first equation), in the same summation
-//                        order as the single-matrix kernels;
+//   k_batch_bounds_pair, k_batch_bounds_rows, k_batch_init_pair,
+//   k_batch_init_final   Gershgorin bounds of (H + H^T)/2 and X_0 with its
+//                        trace (Section "SP2 solver", first equation): the
+//                        pair kernels one workgroup per (matrix, 64 x 64 tile
+//                        pair), the others one per matrix, in the summation
+//                        order of the single-matrix kernels;
 //   k_batch_step<C>      one SP2 step of every matrix still running: one
 //                        workgroup per (matrix, lower tile) item, the FP64 MFMA
 //                        tile and fused epilogue of syrk_f64_core.h, per-tile
@@ -17,7 +19,7 @@
 //                        (the kernel boundary orders the step's writes; an
 //                        in-kernel arrival fence per item measured 3x the
 //                        whole batched solve's time);
-//   k_batch_finalize     D of every matrix;
+//   k_batch_finalize     D of every matrix, one workgroup per block of rows;
 //   k_batch_info         the per-matrix sp2_info records.
 // The plan captures reset, bounds/init, max_iter steps, finalize and info
 // into one graph at creation; a run copies the caller's H/D pointers to the
@@ -81,44 +83,43 @@ __global__ void k_batch_reset(BatchMat* mats, int batch, double tol, int max_ite
 template <typename T>
 __device__ inline double ld_hb(const T* H, size_t idx) { return (double)H[idx]; }
 
-// One workgroup (kThreads) per matrix, the tile pairs in order: the same
-// pair partials, row sums and pair sums as k_bounds_pair / k_bounds_final /
-// k_init_pair / k_init_final, added in the same order, so the plan's X_0 and
-// bounds equal sp2_density's bit for bit.
+// The bounds and X_0 of every matrix in four grouped kernels, the work of
+// k_bounds_pair / k_bounds_final / k_init_pair / k_init_final spread the same
+// way: the pair kernels take one (matrix, tile pair) item per workgroup, the
+// others one workgroup per matrix.  The pair partials, row sums and pair sums
+// are the single-matrix kernels' and are added in the same order, so the
+// plan's X_0 and bounds equal sp2_density's bit for bit.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_batch_bounds_init(const BatchMat* __restrict__ mats) {
-    __shared__ double sA[kBndTile][kBndTile + 1];
-    __shared__ double sB[kBndTile][kBndTile + 1];
+__global__ __launch_bounds__(kThreads) void k_batch_bounds_pair(const BatchMat* __restrict__ mats,
+                                                                const int2* __restrict__ pairs) {
+    typedef typename PairLds<T>::type L;
+    __shared__ L sA[kBndTile][kBndTile + 1];
+    __shared__ L sB[kBndTile][kBndTile + 1];
+    const int2 it = pairs[blockIdx.x];
+    const BatchMat M = mats[it.x];
+    int I, J;
+    tri_tile((unsigned)it.y, I, J);
+    int bad = 0;
+    load_pair((const T*)M.H, M.n, M.n, I, J, sA, sB, bad);
+    __syncthreads();
+    pair_row_partials(M.n, I, J, sA, sB, M.rowpart, M.ldp);
+    if (bad) atomicOr(&M.st->bad, 1);
+}
+
+// Disc ends R_i (the column-tile partials in tile order) and emin / emax of
+// one matrix per workgroup.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_batch_bounds_rows(const BatchMat* __restrict__ mats) {
     __shared__ double red[2][4];
-    __shared__ double bred[4];
-    __shared__ int sbad;
     const BatchMat M = mats[blockIdx.x];
     const T* __restrict__ H = (const T*)M.H;
-    const int n = M.n, ld = M.n, ldp = M.ldp;
-    State* st = M.st;
+    const int n = M.n, ldp = M.ldp, nb = ldp / kBndTile;
     const int tid = threadIdx.x;
-    const int nb = ldp / kBndTile;
-    const unsigned npairs = (unsigned)(nb * (nb + 1) / 2);
-    if (tid == 0) sbad = 0;
-    int bad = 0;
-    for (unsigned p = 0; p < npairs; ++p) {
-        int I, J;
-        tri_tile(p, I, J);
-        __syncthreads();
-        load_pair(H, n, ld, I, J, sA, sB, bad);
-        __syncthreads();
-        pair_row_partials(n, I, J, sA, sB, M.rowpart, ldp);
-    }
-    if (bad) atomicOr(&sbad, 1);
-    // one workgroup per matrix: the barrier's workgroup-scope fence makes the
-    // row partials (global memory) visible to its other threads; an
-    // agent-scope fence here would write back and invalidate the L2s
-    __syncthreads();
     double lo = INFINITY, hi = -INFINITY;
     for (int i = tid; i < n; i += kThreads) {
         double R = 0.0;
         for (int K = 0; K < nb; ++K) R += M.rowpart[(size_t)K * ldp + i];
-        const double c = (double)H[(size_t)i * ld + i];
+        const double c = (double)H[(size_t)i * n + i];
         lo = fmin(lo, c - R);
         hi = fmax(hi, c + R);
     }
@@ -130,37 +131,69 @@ __global__ __launch_bounds__(kThreads) void k_batch_bounds_init(const BatchMat* 
         red[1][w] = hi;
     }
     __syncthreads();
-    const double emin = fmin(fmin(red[0][0], red[0][1]), fmin(red[0][2], red[0][3]));
-    const double emax = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
     if (tid == 0) {
-        st->emin = emin;
-        st->emax = emax;
-        st->bad = sbad;
+        M.st->emin = fmin(fmin(red[0][0], red[0][1]), fmin(red[0][2], red[0][3]));
+        M.st->emax = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
     }
-    const double width = emax - emin;
-    for (unsigned p = 0; p < npairs; ++p) {
-        int I, J;
-        tri_tile(p, I, J);
-        __syncthreads();
-        load_pair(H, n, ld, I, J, sA, sB, bad);
-        __syncthreads();
-        pair_x0(n, ldp, I, J, emax, width, sA, sB, sA, M.x0, bred, M.part, p);
-    }
+}
+
+// X_0 of one (matrix, tile pair) item per workgroup, with the pair's trace
+// and ||X_0||^2 partials.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_batch_init_pair(const BatchMat* __restrict__ mats,
+                                                              const int2* __restrict__ pairs) {
+    typedef typename PairLds<T>::type L;
+    constexpr int kTileElems = kBndTile * (kBndTile + 1);
+    constexpr int kRaw = sizeof(L) == sizeof(double) ? 2 * kTileElems : kTileElems;
+    __shared__ double raw[kRaw];
+    L (*sA)[kBndTile + 1] = (L (*)[kBndTile + 1])raw;
+    L (*sB)[kBndTile + 1] = (L (*)[kBndTile + 1])((L*)raw + kTileElems);
+    double (*sT)[kBndTile + 1] = (double (*)[kBndTile + 1])raw;
+    __shared__ double red[4];
+    const int2 it = pairs[blockIdx.x];
+    const BatchMat M = mats[it.x];
+    int I, J;
+    tri_tile((unsigned)it.y, I, J);
+    const double emax = M.st->emax, width = M.st->emax - M.st->emin;
+    int bad = 0;
+    load_pair((const T*)M.H, M.n, M.n, I, J, sA, sB, bad);
+    __syncthreads();
+    pair_x0(M.n, M.ldp, I, J, emax, width, sA, sB, sT, M.x0, red, M.part, (unsigned)it.y);
+}
+
+// tr X_0 and ||X_0||^2 of one matrix per workgroup (the pair partials in pair
+// order), the start of its loop, and for learned plans the kept copy of X_0.
+__global__ __launch_bounds__(kThreads) void k_batch_init_final(const BatchMat* __restrict__ mats) {
+    __shared__ double red[4];
+    const BatchMat M = mats[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int nb = M.ldp / kBndTile;
+    const int npairs = nb * (nb + 1) / 2;
     if (M.xk) {
-        // keep X_0 for a restart after rejected learned layers
-        __syncthreads();
-        const size_t q = (size_t)ldp * ldp / 4;
-        for (size_t i = tid; i < q; i += kThreads) ((d4*)M.xk)[i] = ((const d4*)M.x0)[i];
+        // keep X_0 for a restart after rejected learned layers (eight loads in
+        // flight per thread)
+        const size_t q = (size_t)M.ldp * M.ldp / 4;
+        const d4* src = (const d4*)M.x0;
+        d4* dst = (d4*)M.xk;
+        constexpr int U = 8;
+        size_t i = tid;
+        for (; i + (U - 1) * kThreads < q; i += U * kThreads) {
+            d4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = src[i + u * kThreads];
+#pragma unroll
+            for (int u = 0; u < U; ++u) dst[i + u * kThreads] = v[u];
+        }
+        for (; i < q; i += kThreads) dst[i] = src[i];
     }
-    __syncthreads();   // the pair sums, read by this workgroup only
     double t = 0.0, f = 0.0;
-    for (unsigned k = tid; k < npairs; k += kThreads) {
+    for (int k = tid; k < npairs; k += kThreads) {
         t += M.part[2 * k + 0];
         f += M.part[2 * k + 1];
     }
-    t = block_sum(t, bred);
-    f = block_sum(f, bred);
-    if (tid == 0) state_after_init(st, t, f);
+    t = block_sum(t, red);
+    f = block_sum(f, red);
+    if (tid == 0) state_after_init(M.st, t, f);
 }
 
 // One SP2 step of every running matrix.  items[b] = (matrix, lower tile) for
@@ -240,23 +273,42 @@ __global__ __launch_bounds__(C::NT) void k_batch_steer(const BatchMat* __restric
     if (tid == 0) sp2_steer_thread0(st, E, TR, F, st->grow);
 }
 
+// D of every matrix: one (matrix, block of kFinRows rows) item per
+// workgroup; a thread's elements of the block are all loaded before the first
+// is stored.
+constexpr int kFinRows = 8;
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_batch_finalize(const BatchMat* __restrict__ mats) {
-    const BatchMat M = mats[blockIdx.x];
+__global__ __launch_bounds__(kThreads) void k_batch_finalize(const BatchMat* __restrict__ mats,
+                                                             const int2* __restrict__ rows) {
+    const int2 it = rows[blockIdx.x];
+    const BatchMat M = mats[it.x];
     const State* st = M.st;
     if (st->status < 0) return;
     const int special = st->special;
     const double* src = (st->iterations & 1) ? M.x1 : M.x0;
     T* D = (T*)M.D;
-    const int n = M.n;
-    for (int i = 0; i < n; ++i)
-        for (int j = threadIdx.x; j < n; j += kThreads) {
-            double v;
-            if (special == 1) v = 0.0;
-            else if (special == 2) v = (i == j) ? 1.0 : 0.0;
-            else v = src[(size_t)i * M.ldp + j];
-            D[(size_t)i * n + j] = (T)v;
+    const int n = M.n, i0 = it.y * kFinRows;
+    const int cnt = (n - i0 < kFinRows ? n - i0 : kFinRows) * n;   // elements of the block, row by row
+    auto put = [&](auto&& value) {
+        constexpr int U = 16;
+        for (int q0 = threadIdx.x; q0 < cnt; q0 += U * kThreads) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * kThreads;
+                v[u] = q < cnt ? value(i0 + q / n, q % n) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * kThreads;
+                if (q < cnt) D[(size_t)i0 * n + q] = (T)v[u];
+            }
         }
+    };
+    if (special == 1) put([](int, int) { return 0.0; });
+    else if (special == 2) put([](int i, int j) { return (i == j) ? 1.0 : 0.0; });
+    else put([&](int i, int j) { return src[(size_t)i * M.ldp + j]; });
 }
 
 __global__ void k_batch_info(const BatchMat* __restrict__ mats, int batch, sp2_info* __restrict__ out) {
@@ -328,6 +380,10 @@ struct sp2_plan {
     sp2::BatchMat* d_mats = nullptr;
     int2* d_items = nullptr;
     int nblocks = 0;
+    int2* d_pairs = nullptr;          // (matrix, 64 x 64 tile pair) items of the bounds and X_0
+    int npairs = 0;
+    int2* d_rows = nullptr;           // (matrix, block of kFinRows rows) items of the finalize
+    int nrows = 0;
     sp2_info* d_infos = nullptr;
     double* d_coef = nullptr;         // learned expansion: 3 per layer
     int n_layers = -1;                // -1: plain SP2
@@ -429,10 +485,20 @@ hipError_t enqueue_solve(sp2_plan* p, hipStream_t s) {
     const int tb = 256;
     hipLaunchKernelGGL(k_batch_reset, dim3((p->batch + tb - 1) / tb), dim3(tb), 0, s, p->d_mats, p->batch,
                        p->tol, p->max_iter, p->n_layers, p->idem_fallback);
-    if (p->dtype == SP2_F64)
-        hipLaunchKernelGGL(k_batch_bounds_init<double>, dim3(p->batch), dim3(kThreads), 0, s, p->d_mats);
-    else
-        hipLaunchKernelGGL(k_batch_bounds_init<float>, dim3(p->batch), dim3(kThreads), 0, s, p->d_mats);
+    if (p->dtype == SP2_F64) {
+        hipLaunchKernelGGL(k_batch_bounds_pair<double>, dim3(p->npairs), dim3(kThreads), 0, s, p->d_mats,
+                           p->d_pairs);
+        hipLaunchKernelGGL(k_batch_bounds_rows<double>, dim3(p->batch), dim3(kThreads), 0, s, p->d_mats);
+        hipLaunchKernelGGL(k_batch_init_pair<double>, dim3(p->npairs), dim3(kThreads), 0, s, p->d_mats,
+                           p->d_pairs);
+    } else {
+        hipLaunchKernelGGL(k_batch_bounds_pair<float>, dim3(p->npairs), dim3(kThreads), 0, s, p->d_mats,
+                           p->d_pairs);
+        hipLaunchKernelGGL(k_batch_bounds_rows<float>, dim3(p->batch), dim3(kThreads), 0, s, p->d_mats);
+        hipLaunchKernelGGL(k_batch_init_pair<float>, dim3(p->npairs), dim3(kThreads), 0, s, p->d_mats,
+                           p->d_pairs);
+    }
+    hipLaunchKernelGGL(k_batch_init_final, dim3(p->batch), dim3(kThreads), 0, s, p->d_mats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int step = 0; step < p->max_iter; ++step) {
@@ -440,9 +506,9 @@ hipError_t enqueue_solve(sp2_plan* p, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     if (p->dtype == SP2_F64)
-        hipLaunchKernelGGL(k_batch_finalize<double>, dim3(p->batch), dim3(kThreads), 0, s, p->d_mats);
+        hipLaunchKernelGGL(k_batch_finalize<double>, dim3(p->nrows), dim3(kThreads), 0, s, p->d_mats, p->d_rows);
     else
-        hipLaunchKernelGGL(k_batch_finalize<float>, dim3(p->batch), dim3(kThreads), 0, s, p->d_mats);
+        hipLaunchKernelGGL(k_batch_finalize<float>, dim3(p->nrows), dim3(kThreads), 0, s, p->d_mats, p->d_rows);
     hipLaunchKernelGGL(k_batch_info, dim3((p->batch + tb - 1) / tb), dim3(tb), 0, s, p->d_mats, p->batch,
                        p->d_infos);
     return hipGetLastError();
@@ -537,6 +603,16 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
     const size_t off_infos = off; off = up256(off + batch * sizeof(sp2_info));
     const size_t off_items = off; off = up256(off + max_items * sizeof(int2));
     const size_t off_tune = off;  off = up256(off + max_items * sizeof(int2));
+    // the bounds / X_0 pair items and the finalize row-block items, plan order
+    std::vector<int2> pairs, rows;
+    for (int k = 0; k < batch; ++k) {
+        const int nb = ldp[k] / kBndTile;
+        for (int q = 0; q < nb * (nb + 1) / 2; ++q) pairs.push_back(make_int2(k, q));
+        const int nk = n[p->order[k]];
+        for (int q = 0; q < (nk + kFinRows - 1) / kFinRows; ++q) rows.push_back(make_int2(k, q));
+    }
+    const size_t off_pairs = off; off = up256(off + pairs.size() * sizeof(int2));
+    const size_t off_rows = off;  off = up256(off + rows.size() * sizeof(int2));
     const size_t off_st = off;    off = up256(off + batch * up256(sizeof(State)));
     const size_t off_coef = off;  off = up256(off + (size_t)3 * (n_layers > 0 ? n_layers : 1) * sizeof(double));
     std::vector<size_t> off_part(batch), off_x(batch), off_rp(batch);
@@ -563,6 +639,10 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
     p->d_infos = (sp2_info*)(base + off_infos);
     p->d_items = (int2*)(base + off_items);
     int2* d_tune = (int2*)(base + off_tune);
+    p->d_pairs = (int2*)(base + off_pairs);
+    p->npairs = (int)pairs.size();
+    p->d_rows = (int2*)(base + off_rows);
+    p->nrows = (int)rows.size();
     p->d_coef = (double*)(base + off_coef);
     for (int k = 0; k < batch; ++k) {
         BatchMat& m = p->h_mats[k];
@@ -586,6 +666,10 @@ int plan_create_impl(sp2_plan** plan, int batch, const int* n, const int* n_occ,
     if (e == hipSuccess) e = prepare_cfg<BCfg32>();
     if (e == hipSuccess) e = hipMemcpyAsync(p->d_mats, p->h_mats, batch * sizeof(BatchMat),
                                             hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_rows, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && n_layers > 0)
         e = hipMemcpy(p->d_coef, coef, (size_t)3 * n_layers * sizeof(double), hipMemcpyHostToDevice);
     // zero iterates: the padding of X stays zero (x^2 and 2x - x^2 keep it)
