@@ -12,8 +12,9 @@
 //                        order of the single-matrix kernels;
 //   k_batch_step<C>      one SP2 step of every matrix still running: one
 //                        workgroup per (matrix, lower tile) item, the FP64 MFMA
-//                        tile and fused epilogue of syrk_f64_core.h, per-tile
-//                        sums, no cross-workgroup fence or counter;
+//                        tile (operands by LDS-DMA) and fused epilogue of
+//                        syrk_f64_core.h, per-tile sums, no cross-workgroup
+//                        fence or counter;
 //   k_batch_steer<C>     after each step, one workgroup per matrix: the
 //                        matrix's tile sums in tile order and its steering
 //                        (the kernel boundary orders the step's writes; an
@@ -224,10 +225,11 @@ __global__ __launch_bounds__(C::NT) void k_batch_step(const BatchMat* __restrict
     for (int mi = 0; mi < C::MI; ++mi)
 #pragma unroll
         for (int ni = 0; ni < C::NI; ++ni) acc[mi][ni] = d4{0.0, 0.0, 0.0, 0.0};
-    double* sA = smem;
-    double* sB = smem + 2 * C::BT * kLDK;
-    if (ti == tj) syrk_mainloop<C, true>(X, ldp, ti, tj, 0, KT, sA, sB, acc);
-    else syrk_mainloop<C, false>(X, ldp, ti, tj, 0, KT, sA, sB, acc);
+    // operands by LDS-DMA (the same MFMAs in the same order as the
+    // register-staged loop of the single-matrix kernel, so the same bits)
+    static_assert(DmaLayout<C>::LDS <= C::LDS, "the launch's LDS holds the DMA stages");
+    if (ti == tj) syrk_mainloop_dma<C, true>(X, ldp, ti, tj, 0, KT, (char*)smem, acc);
+    else syrk_mainloop_dma<C, false>(X, ldp, ti, tj, 0, KT, (char*)smem, acc);
     double e2 = 0.0, trp = 0.0, fro = 0.0;
     if (st->phase == 3) {
         double al, be, ga;

@@ -124,6 +124,17 @@ def test_plan_autotune_cache(sp2, oracle_lib, tmp_path):
     plan2 = sp2.Plan(sizes, nocc, autotune_cache=str(cache))
     assert plan2.config == chosen and cache.read_text().split() == lines
     plan2.close()
+    # each tile shape, forced through the cache entry, against the oracle
+    for shape in ("bt64w4", "bt32w1"):
+        cache.write_text(f"{lines[0]} {shape}\n")
+        plan3 = sp2.Plan(sizes, nocc, autotune_cache=str(cache))
+        assert plan3.config == shape
+        Ds, infos = plan3.run(Ht)
+        for k in (1, 6, 23, 38):
+            ref = oracle_lib.sp2(Hs[k], nocc[k])
+            assert infos[k].status == 0 and infos[k].iterations == ref.iterations, (shape, k)
+            assert rms(Ds[k].cpu().numpy() - ref.D) <= 1e-11, (shape, k)
+        plan3.close()
 
 
 def test_plan_config3_batch(sp2, oracle_lib):
