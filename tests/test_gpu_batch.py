@@ -75,17 +75,25 @@ def test_plan_bitwise_equals_single_solves(sp2, oracle_lib):
 def test_plan_special_and_degenerate_members(sp2):
     inst = make_tb_hamiltonian(64, seed=9)
     Hc = np.eye(32) * 3.0
-    Hs = [inst.H, inst.H, Hc, inst.H]
-    nocc = [0, 64, 10, 32]
+    # non-finite members: a NaN in the only tile pair of an n = 64 matrix, an
+    # Inf in tile pair (2, 0) of an n = 160 matrix (a later pair item)
+    Hnan = inst.H.copy()
+    Hnan[3, 9] = float("nan")
+    Hinf = make_tb_hamiltonian(160, seed=10).H.copy()
+    Hinf[150, 20] = float("inf")
+    Hs = [inst.H, inst.H, Hc, inst.H, Hnan, Hinf]
+    nocc = [0, 64, 10, 32, 32, 80]
     Ht = [torch.from_numpy(H).cuda() for H in Hs]
     Ds = [torch.full_like(h, 7.0) for h in Ht]
-    plan = sp2.Plan([64, 64, 32, 64], nocc)
+    plan = sp2.Plan([64, 64, 32, 64, 64, 160], nocc)
     Ds, infos = plan.run(Ht, Ds)
     assert infos[0].status == 0 and not Ds[0].any()
     assert infos[1].status == 0 and torch.equal(Ds[1], torch.eye(64, dtype=torch.float64, device="cuda"))
     assert infos[2].status == sp2.E_DEGENERATE and bool((Ds[2] == 7.0).all())
     assert infos[3].status == 0
-    assert plan.last_status == sp2.E_DEGENERATE
+    for k in (4, 5):
+        assert infos[k].status == sp2.E_INVALID and bool((Ds[k] == 7.0).all()), k
+    assert plan.last_status == sp2.E_DEGENERATE   # the most negative member status
     plan.close()
 
 
